@@ -1,0 +1,134 @@
+"""Oracle trajectory averages against the Lindblad master equation and closed
+forms, plus invariants of the method (no GPU)."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import oracle
+import workloads as w
+from oracle import closed_forms as cf
+from oracle import lindblad
+
+
+def _within(mean, var, ref, n, k=4.5, floor=1e-6):
+    """|mean - ref| <= k sigma/sqrt(n) + floor at every point."""
+    bound = k * np.sqrt(var / n) + floor
+    return np.all(np.abs(mean - ref) <= bound), np.max(np.abs(mean - ref) / bound)
+
+
+def test_lindblad_routes_agree_with_closed_forms():
+    s = w.two_level()
+    assert np.max(np.abs(lindblad.expect_expm(s)[0] - cf.two_level_sz(s.tlist))) < 1e-13
+    assert np.max(np.abs(lindblad.expect_ode(s)[0] - cf.two_level_sz(s.tlist))) < 1e-8
+    s = w.unitary_example()
+    assert np.max(np.abs(lindblad.expect_expm(s)[0] - cf.unitary_example_sz(s.tlist))) < 1e-13
+    s = w.photon_birth_death()
+    # the Fock cutoff N = 5 changes <n> by at most 2e-5
+    assert np.max(np.abs(lindblad.expect_expm(s)[0] - cf.photon_number(s.tlist))) < 2.5e-5
+    s = w.jaynes_cummings(kappa=0.0, gamma_a=0.0)
+    assert np.max(np.abs(lindblad.expect_expm(s)[1] - cf.jcm_excited_population(s.tlist))) < 1e-12
+
+
+def test_two_level_average_vs_torrey():
+    s = w.two_level()
+    n = 20000
+    res = oracle.run(s, n, seed=0)
+    assert res["status"] == 0
+    ok, worst = _within(res["mean"][0].real, res["var"][0], cf.two_level_sz(s.tlist), n)
+    assert ok, worst
+    # expected number of jumps on [0, 10] is about 2.07
+    assert abs(res["jump_counts"].mean() - 2.07) < 0.05
+
+
+def test_unitary_example_average_vs_closed_form():
+    s = w.unitary_example(c_scale=0.3)
+    n = 8000
+    res = oracle.run(s, n, seed=1)
+    ok, worst = _within(res["mean"][0].real, res["var"][0], cf.unitary_example_sz(s.tlist, 0.3), n)
+    assert ok, worst
+
+
+def test_photon_birth_death_two_channels():
+    """Two channels, one of them a creation operator: the channel statistics
+    enter <n>; checked against the exact truncated Lindblad solution."""
+    s = w.photon_birth_death()
+    n = 20000
+    res = oracle.run(s, n, seed=2)
+    ref = lindblad.expect_expm(s)[0].real
+    ok, worst = _within(res["mean"][0].real, res["var"][0], ref, n)
+    assert ok, worst
+    assert set(np.unique(res["jump_channels"][res["jump_counts"] > 0, 0])) <= {0, 1}
+
+
+def test_jaynes_cummings_vs_lindblad():
+    s = w.jaynes_cummings(t_end=10.0, n_t=101)
+    n = 3000
+    res = oracle.run(s, n, seed=0)
+    ref = lindblad.expect_expm(s)
+    for e in range(2):
+        ok, worst = _within(res["mean"][e].real, res["var"][e], ref[e].real, n)
+        assert ok, (e, worst)
+
+
+def test_small_tfim_vs_lindblad():
+    s = w.tfim(L=4, t_end=5.0, n_t=26)
+    n = 6000
+    res = oracle.run(s, n, seed=4)
+    ref = lindblad.expect_expm(s)
+    for e in range(4):
+        ok, worst = _within(res["mean"][e].real, res["var"][e], ref[e].real, n)
+        assert ok, (e, worst)
+
+
+def test_random_system_vs_lindblad():
+    rng = np.random.Generator(np.random.Philox(key=9))
+    s = w.random_system(rng, 12, 3, t_end=20.0, n_t=41, c_norm=0.3)
+    n = 6000
+    res = oracle.run(s, n, seed=6)
+    ref = lindblad.expect_ode(s)
+    for e in range(2):
+        ok, worst = _within(res["mean"][e].real, res["var"][e], ref[e].real, n)
+        assert ok, (e, worst)
+
+
+# ------------------------------------------------------------ invariants
+def test_identity_observable_and_hermitian_imaginary_part():
+    s = w.jaynes_cummings(N=8, t_end=10.0, n_t=51)
+    s.e_ops = [w.diag(np.ones(s.dim)), s.e_ops[0], w.dense(s.H.to_dense())]
+    res = oracle.run(s, 200, seed=0)
+    assert np.max(np.abs(res["X"][:, 0] - 1.0)) < 1e-13
+    assert np.max(np.abs(res["X"][:, 1:].imag)) < 1e-13
+
+
+def test_no_collapse_operators_is_unitary_evolution():
+    s = w.jaynes_cummings(kappa=0.0, gamma_a=0.0, t_end=10.0, n_t=51)
+    res = oracle.run(s, 3, seed=0, rtol=1e-10, atol=1e-12)
+    assert res["jump_counts"].sum() == 0
+    H = s.H.to_dense()
+    for k, t in enumerate(s.tlist):
+        psi = sla.expm(-1j * H * t) @ s.psi0
+        for e, op in enumerate(s.e_ops):
+            ex = np.vdot(psi, op.to_dense() @ psi).real
+            assert np.all(np.abs(res["X"][:, e, k].real - ex) < 1e-7)
+    assert np.max(np.abs(res["X"][:, 1].real - cf.jcm_excited_population(s.tlist))) < 1e-7
+
+
+def test_norm_non_increasing_between_jumps():
+    s = w.jaynes_cummings(N=10)
+    M = oracle.build_M(s.H, s.c_ops)
+    norms = []
+    for t1 in np.linspace(0.5, 10.0, 20):
+        _, y, _ = oracle.integrate_nojump(M, s.psi0, 0.0, t1)
+        norms.append(np.vdot(y, y).real)
+    norms = np.array(norms)
+    # exact: d||psi||^2/dt = -sum ||C psi||^2 <= 0; numerically within rtol
+    assert np.all(np.diff(norms) <= 1e-6 * norms[1:])
+    assert norms[-1] < norms[0]
+
+
+def test_expected_jumps_jcm():
+    s = w.jaynes_cummings()
+    res = oracle.run(s, 400, seed=0)
+    assert abs(res["jump_counts"].mean() - 4.92) < 0.35
+    st = res["stats"]
+    assert np.all(st[:, 3] == st[:, 4] + 1)  # segments = jumps + 1
