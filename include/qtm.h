@@ -1,0 +1,238 @@
+/*
+ * qtm.h -- C ABI of libqtm.so, a quantum-trajectories (Monte-Carlo wave
+ * function) engine for AMD Instinct MI355X (gfx950).
+ *
+ * The method (the paper's Sec. 2.2): every trajectory evolves a state vector
+ * under the non-Hermitian effective Hamiltonian
+ *     H_eff = H - (i/2) sum_n C_n^dag C_n                (Eq. for H_eff, hbar = 1)
+ * while its squared norm stays at or above a uniform random threshold r;
+ * when the norm falls below r a quantum jump psi <- C_n psi / ||C_n psi||
+ * (Eq. for the post-jump state) takes place, with channel n chosen with
+ * probability P_n proportional to <psi|C_n^dag C_n|psi> (Eq. for P_i), and a
+ * new threshold is drawn (Algorithm 1, steps A-D).  Expectation values
+ * <psi|O|psi>/<psi|psi> are averaged over trajectories (Sec. 3).
+ *
+ * This library integrates d psi/dt = M psi, M = -i H_eff, with the adaptive
+ * Dormand-Prince 5(4) pair and its 4th-order dense output, finds the jump time
+ * as the root of the dense-output norm, draws its random numbers from
+ * counter-based Philox4x64-10 streams (key = (seed, system index), counter =
+ * (trajectory index, segment index, 0, 0); word 0 -> r, word 1 -> channel
+ * uniform, U(x) = ((x >> 11) + 0.5) 2^-53) and averages on the device in FP64.
+ *
+ * Conventions for every entry point:
+ *  - all functions return an int status (QTM_OK or a negative QTM_E_* code)
+ *    unless stated otherwise; on error, qtm_last_error() returns a message
+ *    (thread-local) and no output buffer is written;
+ *  - pointers named in the arguments are HOST pointers unless the name says
+ *    device; the library copies every input it needs, so callers keep
+ *    ownership of their arrays and may free them right after the call;
+ *  - complex numbers are interleaved (re, im) pairs of doubles;
+ *  - no C++ exception crosses this boundary.
+ */
+#ifndef QTM_H
+#define QTM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------- status codes */
+#define QTM_OK        0
+#define QTM_E_INVAL  (-1)   /* invalid argument (shape, value, NaN, ordering) */
+#define QTM_E_NOMEM  (-2)   /* device or host allocation failed */
+#define QTM_E_DEVICE (-3)   /* HIP runtime error, or no gfx950 device */
+#define QTM_E_STEP   (-4)   /* a trajectory hit max_steps or a step-size underflow
+                               (the integrator failure the paper reports as an
+                               error level, Sec. 3 solver wrapper) */
+#define QTM_E_STATE  (-5)   /* call order violated, e.g. qtm_expect before qtm_run */
+
+/* ------------------------------------------------------------- operators */
+#define QTM_FMT_DENSE 0     /* val: dim*dim complex, row-major */
+#define QTM_FMT_CSR   1     /* compressed sparse rows: row_ptr[dim+1], col_ind[nnz], val[nnz] */
+#define QTM_FMT_DIAG  2     /* val: dim complex diagonal entries */
+
+/* An operator on the d-dimensional state space (the paper's dense uMatrix and
+ * sparse uCSRMatrix types, Sec. 3).  Host pointers, FP64 values always; the
+ * storage and precision used on the device are the library's choice. */
+typedef struct {
+    int32_t fmt;              /* QTM_FMT_* */
+    int32_t dim;              /* d */
+    int64_t nnz;              /* CSR only: number of stored entries */
+    const double* val;        /* interleaved complex values */
+    const int32_t* row_ptr;   /* CSR only */
+    const int32_t* col_ind;   /* CSR only, column indices in [0, d) */
+} qtm_op;
+
+/* ------------------------------------------------------------- options */
+#define QTM_PREC_FP64   0     /* every product in FP64 (the plain form) */
+#define QTM_PREC_FP32   1     /* H_eff products in FP32 with FP32 accumulation; state,
+                                 stage sums, norms, root finding and averages in FP64 */
+
+#define QTM_FORM_LEARNED 1u   /* segment start step from the trained MLP proposal */
+#define QTM_FORM_BATCHED 2u   /* persistent kernel with per-slot trajectory refill and
+                                 autotuned tiles (otherwise: one workgroup per block of
+                                 trajectories, no refill) */
+
+typedef struct {
+    double rtol;              /* relative tolerance (default 1e-6) */
+    double atol;              /* absolute tolerance (default 1e-8) */
+    int32_t precision;        /* QTM_PREC_* (default FP64) */
+    uint32_t form;            /* OR of QTM_FORM_* (default 0: plain) */
+    int64_t max_steps;        /* attempted steps per trajectory before QTM_E_STEP (default 1e6) */
+    int32_t device;           /* HIP device ordinal (default 0) */
+    int32_t record_jumps;     /* jump-log capacity per trajectory (0: off) */
+    void* stream;             /* hipStream_t to run on, NULL: the null stream */
+    int32_t keep_traj;        /* keep per-trajectory expectation values (qtm_traj_expect) */
+    int32_t seg_cap;          /* segment records per trajectory for proposal training (0: off) */
+    int32_t tile_cols;        /* 0: autotuned; else columns (trajectories) per workgroup */
+    int32_t reserved[7];
+} qtm_opts;
+
+/* Per-run statistics (summed over trajectories of the last qtm_run). */
+typedef struct {
+    int64_t ntraj;
+    int64_t accepted;         /* accepted DOPRI5 steps */
+    int64_t rejected;         /* rejected DOPRI5 steps */
+    int64_t segments;         /* segments (= jumps + trajectories, unless failed) */
+    int64_t jumps;
+    int64_t rhs_evals;        /* products M w evaluated (per trajectory-column) */
+    int64_t passes;           /* block-wide product passes executed by the kernel */
+    int64_t failed_traj;      /* smallest failing trajectory index, -1 if none */
+    double kernel_ms;         /* device time of the trajectory kernel(s) */
+    double elapsed_ms;        /* host wall time of qtm_run */
+    int32_t blocks, threads, tile_cols, lds_bytes;   /* launch configuration used */
+} qtm_stats_t;
+
+/* A system for qtm_create_batch (same meaning as the qtm_create arguments). */
+typedef struct {
+    const qtm_op* H;
+    const qtm_op* c_ops;
+    int32_t n_c;
+    const double* psi0;
+    const double* tlist;
+    int32_t n_t;
+    const qtm_op* e_ops;
+    int32_t n_e;
+} qtm_system;
+
+typedef struct qtm_ctx qtm_ctx;
+
+/* Fills *o with the defaults listed above. */
+void qtm_opts_default(qtm_opts* o);
+
+/* Creates a context for one system (the problem statement of the paper's
+ * examples, Sec. 4: Hamiltonian, collapse operators, initial state, output
+ * times, expectation operators).
+ *   H       d x d Hermitian operator (any format).  A CSR H selects the sparse
+ *           kernel; a dense H (d <= 256) the MFMA kernel.
+ *   c_ops   n_c collapse operators C_n (0 <= n_c <= 16), d x d, any format.
+ *   psi0    d complex amplitudes with | ||psi0|| - 1 | <= 1e-10.
+ *   tlist   n_t >= 2 strictly increasing output times; tlist[0] is the start
+ *           time t0 and tlist[n_t-1] the end time.
+ *   e_ops   n_e (1..16) expectation operators O_k (any format).
+ *   o       options (NULL: defaults).
+ * Builds M = -i H - 1/2 sum C_n^dag C_n on the host in FP64 and uploads it.
+ * Errors: QTM_E_INVAL (shape, non-finite entry, bad norm, bad tlist, index
+ * out of range), QTM_E_NOMEM, QTM_E_DEVICE. */
+int qtm_create(qtm_ctx** out, const qtm_op* H, const qtm_op* c_ops, int32_t n_c, const double* psi0,
+               const double* tlist, int32_t n_t, const qtm_op* e_ops, int32_t n_e, const qtm_opts* o);
+
+/* Creates a context holding n_sys systems of mixed dimension (each dense,
+ * d <= 256, n_e <= 16) that qtm_run integrates in one persistent launch per
+ * tile class.  System s uses Philox key (seed, s).  Errors as qtm_create; the
+ * message names the offending system index. */
+int qtm_create_batch(qtm_ctx** out, int32_t n_sys, const qtm_system* sys, const qtm_opts* o);
+
+/* Runs trajectories 0..ntraj-1 (of every system of a batch) on the context's
+ * stream and waits for them.  Equivalent to qtm_run_range(ctx, 0, ntraj, seed).
+ * Errors: QTM_E_INVAL (ntraj < 1), QTM_E_NOMEM, QTM_E_DEVICE, QTM_E_STEP (one
+ * or more trajectories failed; qtm_stats names the smallest index; averages are
+ * then not available). */
+int qtm_run(qtm_ctx* ctx, int64_t ntraj, uint64_t seed);
+
+/* Runs trajectories traj_begin .. traj_begin+count-1.  Because the random
+ * stream of trajectory i depends only on (seed, system, i), the sums of
+ * disjoint ranges combine into the sums of their union (sharding property). */
+int qtm_run_range(qtm_ctx* ctx, int64_t traj_begin, int64_t count, uint64_t seed);
+
+/* Trajectory averages of the last run (of system 0 for a batch):
+ *   mean [n_e][n_t] complex (interleaved), var [n_e][n_t] variance of the real
+ *   part over trajectories (nullable).  Host buffers, caller-allocated.
+ * Errors: QTM_E_STATE before a successful qtm_run. */
+int qtm_expect(const qtm_ctx* ctx, double* mean, double* var);
+
+/* Same for system s of a batch context. */
+int qtm_expect_system(const qtm_ctx* ctx, int32_t s, double* mean, double* var);
+
+/* The running sums behind the averages: sum [n_e][n_t] complex, sumsq
+ * [n_e][n_t] (of the real part) and the trajectory count, in FP64; sums of
+ * disjoint trajectory ranges add. */
+int qtm_sums(const qtm_ctx* ctx, int32_t s, double* sum, double* sumsq, int64_t* count);
+
+/* Per-trajectory expectation values of the last run (requires keep_traj):
+ * X [count][n_e][n_t] complex for system s. */
+int qtm_traj_expect(const qtm_ctx* ctx, int32_t s, double* X);
+
+/* Jump log of trajectory traj (index within the last run's range) of system s
+ * (requires record_jumps > 0): up to cap (time, channel) pairs; *count
+ * receives the total number of jumps (which may exceed the log capacity). */
+int qtm_jumps(const qtm_ctx* ctx, int32_t s, int64_t traj, int32_t cap, double* times, int32_t* channels,
+              int32_t* count);
+
+/* Per-trajectory counters of the last run: [count][4] = accepted steps,
+ * rejected steps, segments, jumps (int32), for system s. */
+int qtm_traj_stats(const qtm_ctx* ctx, int32_t s, int32_t* stats);
+
+/* Statistics of the last run. */
+int qtm_stats(const qtm_ctx* ctx, qtm_stats_t* st);
+
+/* ---------------------------------------------------- learned proposal */
+/* The proposal network maps 16 segment-start features to (log h0, log tau_lo,
+ * log tau_hi): features are 12 diagonal-observable expectations (the f_ops
+ * given to qtm_set_proposal), <C_0^dag C_0>, <C_1^dag C_1>, log r and the
+ * elapsed fraction of the time span; architecture 16 -> 64 -> 64 -> 3 with
+ * GELU, BF16 weights and FP32 accumulation.  The proposed h0 is snapped to the
+ * grid 2^(k/4) and replaces the starting-step rule; the exact root finding of
+ * the jump time is unchanged. */
+#define QTM_MLP_NPARAM 5443   /* trainable parameters (W1,b1,W2,b2,W3,b3) */
+#define QTM_MLP_NTOTAL 5475   /* + input mean[16] and scale[16] */
+
+/* Installs proposal weights (FP32 masters, QTM_MLP_NTOTAL values, host) and
+ * the feature operators (n_f <= 12 diagonal operators). */
+int qtm_set_proposal(qtm_ctx* ctx, const float* params, int32_t n_params, const qtm_op* f_ops, int32_t n_f);
+
+/* Copies the current proposal weights (FP32 masters) to params (host). */
+int qtm_get_proposal(const qtm_ctx* ctx, float* params, int32_t n_params);
+
+/* Segment records of the last run (requires seg_cap > 0): [count][seg_cap][20]
+ * floats = 16 features, realised jump delay tau, the controller's step after the
+ * first accepted step, censored flag, valid flag. */
+int qtm_segments(const qtm_ctx* ctx, float* out);
+
+/* Trains the proposal on the device with the library's forward/backward/Adam
+ * kernels.  feat [n][16], tgt [n][3] (log h*, log tau, censored flag) are host
+ * FP32 arrays; the loss is the mean of (o0 - log h*)^2 plus, for uncensored
+ * samples, the pinball losses at quantiles 0.05 and 0.95 of log tau.  Writes the
+ * mean loss of each epoch to loss_out (nullable, n_epochs values). */
+int qtm_train_proposal(qtm_ctx* ctx, const float* feat, const float* tgt, int64_t n, int32_t n_epochs,
+                       int32_t batch, float lr, uint64_t shuffle_seed, float* loss_out);
+
+/* Loss and gradient of the proposal on one batch with the current weights,
+ * computed by the device forward and backward kernels (BF16 weights, FP32
+ * activations): grad receives QTM_MLP_NPARAM floats (host). */
+int qtm_proposal_grad(qtm_ctx* ctx, const float* feat, const float* tgt, int64_t n, float* loss, float* grad);
+
+/* ----------------------------------------------------------- misc */
+/* Message of the last failing call in this thread ("" if none).  Not an int. */
+const char* qtm_last_error(void);
+
+/* Frees every device and host resource of the context.  Not an int; NULL is a no-op. */
+void qtm_destroy(qtm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QTM_H */

@@ -1,0 +1,869 @@
+// qtm_capi.cpp -- host runtime and C ABI of libqtm (declared in include/qtm.h).
+//
+// qtm_create validates the problem, assembles the right-hand-side operator
+// M = -i H - 1/2 sum_n C_n^dag C_n (= -i H_eff, the paper's effective
+// Hamiltonian with hbar = 1) in FP64 on the host, lays it out for the chosen
+// kernel (MFMA A-fragments for dense M, 64-row sliced ELL for sparse M) and
+// uploads everything once.  qtm_run launches the trajectory kernel on the
+// context's stream, then the index-ordered averaging kernel.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <complex>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/qtm.h"
+#include "qtm_internal.h"
+
+using cd = std::complex<double>;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHECK(x)                                                                        \
+    do {                                                                                   \
+        hipError_t e_ = (x);                                                               \
+        if (e_ != hipSuccess) return fail(QTM_E_DEVICE, "%s: %s", #x, hipGetErrorString(e_)); \
+    } while (0)
+
+// Host CSR with complex values.
+struct HCsr {
+    int d = 0;
+    std::vector<int> rp, ci;
+    std::vector<cd> v;
+};
+
+int validate_op(const qtm_op* o, int d, const char* what, int idx) {
+    if (!o) return fail(QTM_E_INVAL, "%s[%d]: null operator", what, idx);
+    if (o->dim != d) return fail(QTM_E_INVAL, "%s[%d]: dimension %d, expected %d", what, idx, o->dim, d);
+    if (!o->val) return fail(QTM_E_INVAL, "%s[%d]: null values", what, idx);
+    size_t n = 0;
+    if (o->fmt == QTM_FMT_DENSE) n = (size_t)d * d;
+    else if (o->fmt == QTM_FMT_DIAG) n = (size_t)d;
+    else if (o->fmt == QTM_FMT_CSR) {
+        if (!o->row_ptr || !o->col_ind) return fail(QTM_E_INVAL, "%s[%d]: CSR without row_ptr/col_ind", what, idx);
+        if (o->row_ptr[0] != 0 || o->row_ptr[d] != o->nnz || o->nnz < 0)
+            return fail(QTM_E_INVAL, "%s[%d]: CSR row_ptr[0] must be 0 and row_ptr[d] == nnz", what, idx);
+        for (int i = 0; i < d; ++i)
+            if (o->row_ptr[i + 1] < o->row_ptr[i]) return fail(QTM_E_INVAL, "%s[%d]: CSR row_ptr not non-decreasing", what, idx);
+        for (int64_t p = 0; p < o->nnz; ++p)
+            if (o->col_ind[p] < 0 || o->col_ind[p] >= d)
+                return fail(QTM_E_INVAL, "%s[%d]: CSR column index %d out of range", what, idx, o->col_ind[p]);
+        n = (size_t)o->nnz;
+    } else {
+        return fail(QTM_E_INVAL, "%s[%d]: unknown format %d", what, idx, o->fmt);
+    }
+    for (size_t i = 0; i < 2 * n; ++i)
+        if (!std::isfinite(o->val[i])) return fail(QTM_E_INVAL, "%s[%d]: non-finite entry", what, idx);
+    return QTM_OK;
+}
+
+HCsr to_csr(const qtm_op* o, bool drop_zeros) {
+    HCsr c;
+    int d = o->dim;
+    c.d = d;
+    c.rp.assign(d + 1, 0);
+    if (o->fmt == QTM_FMT_CSR) {
+        c.rp.assign(o->row_ptr, o->row_ptr + d + 1);
+        c.ci.assign(o->col_ind, o->col_ind + o->nnz);
+        for (int64_t p = 0; p < o->nnz; ++p) c.v.push_back(cd(o->val[2 * p], o->val[2 * p + 1]));
+        return c;
+    }
+    for (int i = 0; i < d; ++i) {
+        if (o->fmt == QTM_FMT_DIAG) {
+            cd z(o->val[2 * i], o->val[2 * i + 1]);
+            if (!drop_zeros || z != 0.0) { c.ci.push_back(i); c.v.push_back(z); }
+        } else {
+            for (int j = 0; j < d; ++j) {
+                cd z(o->val[2 * ((size_t)i * d + j)], o->val[2 * ((size_t)i * d + j) + 1]);
+                if (!drop_zeros || z != 0.0) { c.ci.push_back(j); c.v.push_back(z); }
+            }
+        }
+        c.rp[i + 1] = (int)c.ci.size();
+    }
+    return c;
+}
+
+// M = -i H - 1/2 sum_n C_n^dag C_n as CSR (rows accumulated in a dense buffer).
+HCsr build_M(const qtm_op* H, const qtm_op* c, int n_c) {
+    const int d = H->dim;
+    HCsr h = to_csr(H, false);
+    std::vector<HCsr> C;
+    for (int n = 0; n < n_c; ++n) C.push_back(to_csr(&c[n], true));
+    // (C^dag C)_{pq} = sum_k conj(C_kp) C_kq: contributions per row p
+    std::vector<std::vector<std::pair<int, cd>>> extra(d);
+    for (const HCsr& m : C)
+        for (int k = 0; k < d; ++k)
+            for (int a = m.rp[k]; a < m.rp[k + 1]; ++a)
+                for (int b = m.rp[k]; b < m.rp[k + 1]; ++b)
+                    extra[m.ci[a]].push_back({m.ci[b], -0.5 * std::conj(m.v[a]) * m.v[b]});
+    HCsr M;
+    M.d = d;
+    M.rp.assign(d + 1, 0);
+    std::vector<cd> acc(d, 0.0);
+    std::vector<char> used(d, 0);
+    std::vector<int> cols;
+    for (int i = 0; i < d; ++i) {
+        cols.clear();
+        for (int p = h.rp[i]; p < h.rp[i + 1]; ++p) {
+            int j = h.ci[p];
+            if (!used[j]) { used[j] = 1; cols.push_back(j); }
+            acc[j] += cd(0.0, -1.0) * h.v[p];
+        }
+        for (auto& e : extra[i]) {
+            if (!used[e.first]) { used[e.first] = 1; cols.push_back(e.first); }
+            acc[e.first] += e.second;
+        }
+        std::sort(cols.begin(), cols.end());
+        for (int j : cols) { M.ci.push_back(j); M.v.push_back(acc[j]); acc[j] = 0.0; used[j] = 0; }
+        M.rp[i + 1] = (int)M.ci.size();
+    }
+    return M;
+}
+
+// MFMA A-fragments of the real-embedded operator (see the row maps in the kernels):
+// frag[(rt*KB + kb)*64 + lane] = Mreal[16 rt + (lane & 15)][4 kb + (lane >> 4)].
+int row_of(int q, int p, int prec) {
+    if (prec == 0) return 16 * (q >> 3) + 4 * (2 * ((q & 7) >> 2) + p) + (q & 3);
+    return 2 * q + p;
+}
+
+template <class T>
+std::vector<T> build_frag(const HCsr& M, int dp, int prec) {
+    const int n = 2 * dp, KB = n / 4, RT = n / 16;
+    std::vector<double> real((size_t)n * n, 0.0);
+    for (int i = 0; i < M.d; ++i)
+        for (int p = M.rp[i]; p < M.rp[i + 1]; ++p) {
+            int j = M.ci[p];
+            double re = M.v[p].real(), im = M.v[p].imag();
+            real[(size_t)row_of(i, 0, prec) * n + row_of(j, 0, prec)] += re;
+            real[(size_t)row_of(i, 0, prec) * n + row_of(j, 1, prec)] += -im;
+            real[(size_t)row_of(i, 1, prec) * n + row_of(j, 0, prec)] += im;
+            real[(size_t)row_of(i, 1, prec) * n + row_of(j, 1, prec)] += re;
+        }
+    std::vector<T> f((size_t)n * n);
+    for (int rt = 0; rt < RT; ++rt)
+        for (int kb = 0; kb < KB; ++kb)
+            for (int l = 0; l < 64; ++l)
+                f[((size_t)rt * KB + kb) * 64 + l] = (T)real[(size_t)(16 * rt + (l & 15)) * n + 4 * kb + (l >> 4)];
+    return f;
+}
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t n = 0;
+};
+
+struct SysHost {
+    int d = 0, n_c = 0, n_e = 0, n_t = 0, n_f = 0;
+    bool sparse = false;
+    qtm::DevSystem dev{};
+    std::vector<double> tlist;
+    std::vector<DevBuf> bufs;          // device allocations owned by the system
+    // run outputs
+    DevBuf X, tstat, jt, jc, jn, segs, queue, sum, sumsq;
+    long long cap_count = 0;
+    std::vector<double> h_sum, h_sumsq;
+    long long sum_count = 0;
+};
+
+}  // namespace
+
+struct qtm_ctx {
+    qtm_opts o{};
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::vector<SysHost> sys;
+    qtm::DevSystem* d_sys = nullptr;   // device copy of the DevSystem array
+    long long* d_fail = nullptr;
+    unsigned long long* d_counters = nullptr;
+    unsigned int* d_cursor = nullptr;
+    float* d_mlp = nullptr;            // BF16-rounded weights for inference
+    std::vector<float> mlp_master;     // FP32 master weights
+    bool have_mlp = false;
+    bool ran = false;
+    qtm_stats_t st{};
+    long long last_begin = 0, last_count = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    int ncu = 0;
+};
+
+namespace {
+
+int dalloc(SysHost& s, void** p, size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) return fail(QTM_E_NOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    s.bufs.push_back({*p, bytes});
+    return QTM_OK;
+}
+
+template <class T>
+int upload(SysHost& s, const T** out, const std::vector<T>& v) {
+    void* p = nullptr;
+    int rc = dalloc(s, &p, v.size() * sizeof(T));
+    if (rc) return rc;
+    if (!v.empty()) HIPCHECK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    *out = (const T*)p;
+    return QTM_OK;
+}
+
+void free_buf(DevBuf& b) {
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.n = 0;
+}
+
+int ensure_buf(DevBuf& b, size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    if (b.n >= bytes) return QTM_OK;
+    free_buf(b);
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) { b.p = nullptr; return fail(QTM_E_NOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e)); }
+    b.n = bytes;
+    return QTM_OK;
+}
+
+int setup_system(SysHost& S, const qtm_system& in, int idx, const qtm_opts& o, bool allow_sparse) {
+    const qtm_op* H = in.H;
+    if (!H) return fail(QTM_E_INVAL, "system %d: null H", idx);
+    const int d = H->dim;
+    if (d < 1) return fail(QTM_E_INVAL, "system %d: dimension %d < 1", idx, d);
+    int rc = validate_op(H, d, "H", 0);
+    if (rc) return rc;
+    if (in.n_c < 0 || in.n_c > qtm::kMaxC) return fail(QTM_E_INVAL, "system %d: n_c = %d outside [0, %d]", idx, in.n_c, qtm::kMaxC);
+    if (in.n_c > 0 && !in.c_ops) return fail(QTM_E_INVAL, "system %d: null c_ops", idx);
+    for (int n = 0; n < in.n_c; ++n) if ((rc = validate_op(&in.c_ops[n], d, "c_ops", n))) return rc;
+    if (in.n_e < 1 || in.n_e > qtm::kMaxE) return fail(QTM_E_INVAL, "system %d: n_e = %d outside [1, %d]", idx, in.n_e, qtm::kMaxE);
+    if (!in.e_ops) return fail(QTM_E_INVAL, "system %d: null e_ops", idx);
+    for (int n = 0; n < in.n_e; ++n) if ((rc = validate_op(&in.e_ops[n], d, "e_ops", n))) return rc;
+    if (!in.psi0) return fail(QTM_E_INVAL, "system %d: null psi0", idx);
+    double nn = 0.0;
+    for (int i = 0; i < 2 * d; ++i) {
+        if (!std::isfinite(in.psi0[i])) return fail(QTM_E_INVAL, "system %d: non-finite psi0", idx);
+        nn += in.psi0[i] * in.psi0[i];
+    }
+    if (std::fabs(std::sqrt(nn) - 1.0) > 1e-10) return fail(QTM_E_INVAL, "system %d: ||psi0|| = %.17g, not 1", idx, std::sqrt(nn));
+    if (in.n_t < 2 || !in.tlist) return fail(QTM_E_INVAL, "system %d: need n_t >= 2 output times", idx);
+    for (int k = 0; k < in.n_t; ++k) {
+        if (!std::isfinite(in.tlist[k])) return fail(QTM_E_INVAL, "system %d: non-finite tlist", idx);
+        if (k > 0 && !(in.tlist[k] > in.tlist[k - 1])) return fail(QTM_E_INVAL, "system %d: tlist not strictly increasing at %d", idx, k);
+    }
+    S.sparse = allow_sparse && H->fmt == QTM_FMT_CSR;
+    if (!S.sparse && d > 128) return fail(QTM_E_INVAL, "system %d: dense kernels support d <= 128 (got %d); pass H in CSR", idx, d);
+    if (S.sparse && d > 2048) return fail(QTM_E_INVAL, "system %d: sparse kernel supports d <= 2048 (got %d)", idx, d);
+    S.d = d; S.n_c = in.n_c; S.n_e = in.n_e; S.n_t = in.n_t;
+    S.tlist.assign(in.tlist, in.tlist + in.n_t);
+    qtm::DevSystem& D = S.dev;
+    std::memset(&D, 0, sizeof(D));
+    D.d = d; D.n_c = in.n_c; D.n_e = in.n_e; D.n_t = in.n_t; D.n_f = 0;
+    D.t0 = in.tlist[0]; D.tend = in.tlist[in.n_t - 1];
+    D.key1 = (unsigned long long)idx;
+    HCsr M = build_M(H, in.c_ops, in.n_c);
+    if (!S.sparse) {
+        int dp = (d + 7) / 8 * 8;
+        D.dp = dp;
+        D.rt = 2 * dp / 16;
+        if ((rc = upload(S, &D.Mfrag, build_frag<double>(M, dp, 0)))) return rc;
+        if ((rc = upload(S, &D.Mfrag32, build_frag<float>(M, dp, 1)))) return rc;
+    } else {
+        D.dp = d;
+        int nsl = (d + 63) / 64;
+        std::vector<int> off(nsl + 1, 0), wd(nsl, 0);
+        for (int s = 0; s < nsl; ++s) {
+            int w = 0;
+            for (int i = 64 * s; i < std::min(d, 64 * s + 64); ++i) w = std::max(w, M.rp[i + 1] - M.rp[i]);
+            wd[s] = w;
+            off[s + 1] = off[s] + 64 * w;
+        }
+        std::vector<int> col(off[nsl], 0);
+        std::vector<double2> val(off[nsl], make_double2(0.0, 0.0));
+        std::vector<float2> val32(off[nsl], make_float2(0.f, 0.f));
+        for (int s = 0; s < nsl; ++s)
+            for (int i = 64 * s; i < std::min(d, 64 * s + 64); ++i) {
+                int ln = i - 64 * s;
+                for (int p = M.rp[i], k = 0; p < M.rp[i + 1]; ++p, ++k) {
+                    int idx2 = off[s] + k * 64 + ln;
+                    col[idx2] = M.ci[p];
+                    val[idx2] = make_double2(M.v[p].real(), M.v[p].imag());
+                    val32[idx2] = make_float2((float)M.v[p].real(), (float)M.v[p].imag());
+                }
+                // padding entries: column of the row itself with value 0 (in range, harmless)
+                for (int k = M.rp[i + 1] - M.rp[i]; k < wd[s]; ++k) col[off[s] + k * 64 + ln] = i;
+            }
+        // rows past d in the last slice point at row 0 with zero values
+        if ((rc = upload(S, &D.sl_off, off))) return rc;
+        if ((rc = upload(S, &D.sl_w, wd))) return rc;
+        if ((rc = upload(S, &D.sl_col, col))) return rc;
+        if ((rc = upload(S, &D.sl_val, val))) return rc;
+        if ((rc = upload(S, &D.sl_val32, val32))) return rc;
+    }
+    // collapse operators: CSR with absolute row pointers
+    {
+        std::vector<int> rp, ci;
+        std::vector<double2> v;
+        for (int n = 0; n < in.n_c; ++n) {
+            HCsr c = to_csr(&in.c_ops[n], true);
+            int base = (int)ci.size();
+            for (int i = 0; i <= d; ++i) rp.push_back(base + c.rp[i]);
+            for (size_t p = 0; p < c.ci.size(); ++p) { ci.push_back(c.ci[p]); v.push_back(make_double2(c.v[p].real(), c.v[p].imag())); }
+        }
+        if (rp.empty()) rp.push_back(0);
+        if ((rc = upload(S, &D.c_rp, rp))) return rc;
+        if ((rc = upload(S, &D.c_ci, ci))) return rc;
+        if ((rc = upload(S, &D.c_val, v))) return rc;
+    }
+    // observables: diagonal ones keep their diagonal, others become CSR
+    {
+        std::vector<int> rp, ci;
+        std::vector<double2> v;
+        for (int e = 0; e < in.n_e; ++e) {
+            const qtm_op* O = &in.e_ops[e];
+            if (O->fmt == QTM_FMT_DIAG) {
+                D.e_fmt[e] = 2;
+                D.e_doff[e] = (int)v.size();
+                bool real = true;
+                for (int i = 0; i < d; ++i) {
+                    v.push_back(make_double2(O->val[2 * i], O->val[2 * i + 1]));
+                    if (O->val[2 * i + 1] != 0.0) real = false;
+                }
+                D.e_nv[e] = real ? 1 : 2;
+                for (int i = 0; i <= d; ++i) rp.push_back(0);
+            } else {
+                D.e_fmt[e] = 1;
+                D.e_nv[e] = 2;
+                D.any_csr_e = 1;
+                HCsr c = to_csr(O, true);
+                int base = (int)v.size();
+                // CSR values appended after any diagonal block; column indices parallel to values
+                ci.resize(v.size(), 0);
+                for (int i = 0; i <= d; ++i) rp.push_back(base + c.rp[i]);
+                for (size_t p = 0; p < c.ci.size(); ++p) { v.push_back(make_double2(c.v[p].real(), c.v[p].imag())); ci.push_back(c.ci[p]); }
+            }
+        }
+        ci.resize(v.size(), 0);
+        if ((rc = upload(S, &D.e_rp, rp))) return rc;
+        if ((rc = upload(S, &D.e_ci, ci))) return rc;
+        if ((rc = upload(S, &D.e_val, v))) return rc;
+    }
+    {
+        std::vector<double2> p0(d);
+        for (int i = 0; i < d; ++i) p0[i] = make_double2(in.psi0[2 * i], in.psi0[2 * i + 1]);
+        if ((rc = upload(S, &D.psi0, p0))) return rc;
+        if ((rc = upload(S, &D.tlist, S.tlist))) return rc;
+        std::vector<double> fd((size_t)12 * d, 0.0);
+        if ((rc = upload(S, &D.f_diag, fd))) return rc;
+    }
+    (void)o;
+    return QTM_OK;
+}
+
+float bf16_round(float x) {
+    uint32_t u;
+    std::memcpy(&u, &x, 4);
+    uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7FFFu + lsb;          // round to nearest even
+    u &= 0xFFFF0000u;
+    float r;
+    std::memcpy(&r, &u, 4);
+    return r;
+}
+
+int check_ctx(const qtm_ctx* c) {
+    if (!c) return fail(QTM_E_INVAL, "null context");
+    return QTM_OK;
+}
+
+
+// Host-side standardisation and initial weights for training from scratch.
+void init_proposal(std::vector<float>& P, const float* feat, const float* tgt, int64_t n, uint64_t seed) {
+    P.assign(qtm::kNTotal, 0.f);
+    const int NF = qtm::kNF, NH = qtm::kNH, NO = qtm::kNO;
+    const int oW1 = 0, ob1 = NH * NF, oW2 = ob1 + NH, ob2 = oW2 + NH * NH, oW3 = ob2 + NH, ob3 = oW3 + NO * NH;
+    const int omu = ob3 + NO, osd = omu + NF;
+    for (int i = 0; i < NF; ++i) {
+        double s = 0.0, s2 = 0.0;
+        for (int64_t q = 0; q < n; ++q) { double x = feat[q * NF + i]; s += x; s2 += x * x; }
+        double mu = s / (double)n, var = s2 / (double)n - mu * mu;
+        P[omu + i] = (float)mu;
+        P[osd + i] = (float)std::max(1e-3, std::sqrt(std::max(0.0, var)));
+    }
+    // splitmix64 stream for the initial weights (uniform, fan-in scaled)
+    uint64_t x = seed ^ 0x5DEECE66DULL;
+    auto uni = [&]() {
+        x += 0x9E3779B97F4A7C15ULL;
+        uint64_t z = x;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+        z ^= z >> 31;
+        return ((double)(z >> 11) + 0.5) * 0x1.0p-53;
+    };
+    auto fill = [&](int off, int cnt, int fan_in) {
+        double a = std::sqrt(3.0 / fan_in);
+        for (int i = 0; i < cnt; ++i) P[off + i] = (float)((2.0 * uni() - 1.0) * a);
+    };
+    fill(oW1, NH * NF, NF);
+    fill(oW2, NH * NH, NH);
+    fill(oW3, NO * NH, NH);
+    // output biases start at the target means
+    double m0 = 0.0, m1 = 0.0;
+    int64_t n1 = 0;
+    for (int64_t q = 0; q < n; ++q) {
+        m0 += tgt[q * 3];
+        if (tgt[q * 3 + 2] == 0.f) { m1 += tgt[q * 3 + 1]; ++n1; }
+    }
+    P[ob3 + 0] = (float)(m0 / (double)n);
+    P[ob3 + 1] = P[ob3 + 2] = (float)(n1 ? m1 / (double)n1 : 0.0);
+}
+
+void working_copy(const std::vector<float>& master, std::vector<float>& q) {
+    q = master;
+    const int nW1 = qtm::kNH * qtm::kNF, nW2 = qtm::kNH * qtm::kNH, nW3 = qtm::kNO * qtm::kNH;
+    const int oW1 = 0, oW2 = nW1 + qtm::kNH, oW3 = oW2 + nW2 + qtm::kNH;
+    for (int i = 0; i < nW1; ++i) q[oW1 + i] = bf16_round(q[oW1 + i]);
+    for (int i = 0; i < nW2; ++i) q[oW2 + i] = bf16_round(q[oW2 + i]);
+    for (int i = 0; i < nW3; ++i) q[oW3 + i] = bf16_round(q[oW3 + i]);
+}
+
+struct DevScratch {
+    std::vector<void*> ptrs;
+    ~DevScratch() { for (void* p : ptrs) if (p) (void)hipFree(p); }
+    template <class T> int get(T** p, size_t n) {
+        if (hipMalloc((void**)p, sizeof(T) * std::max<size_t>(n, 1)) != hipSuccess) return -2;
+        ptrs.push_back(*p);
+        return 0;
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+void qtm_opts_default(qtm_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->rtol = 1e-6;
+    o->atol = 1e-8;
+    o->precision = QTM_PREC_FP64;
+    o->form = 0;
+    o->max_steps = 1000000;
+    o->device = 0;
+    o->record_jumps = 0;
+    o->stream = nullptr;
+}
+
+const char* qtm_last_error(void) { return g_err.c_str(); }
+
+static int create_common(qtm_ctx** out, int32_t n_sys, const qtm_system* sys, const qtm_opts* o, bool allow_sparse) {
+    if (!out) return fail(QTM_E_INVAL, "null output pointer");
+    *out = nullptr;
+    qtm_opts opt;
+    if (o) opt = *o; else qtm_opts_default(&opt);
+    if (!(opt.rtol > 0.0) || !(opt.atol >= 0.0) || !std::isfinite(opt.rtol) || !std::isfinite(opt.atol))
+        return fail(QTM_E_INVAL, "rtol must be > 0 and atol >= 0");
+    if (opt.precision != QTM_PREC_FP64 && opt.precision != QTM_PREC_FP32) return fail(QTM_E_INVAL, "unknown precision %d", opt.precision);
+    if (opt.max_steps < 1) return fail(QTM_E_INVAL, "max_steps must be >= 1");
+    if (opt.record_jumps < 0 || opt.seg_cap < 0) return fail(QTM_E_INVAL, "negative capacity");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(QTM_E_DEVICE, "no HIP device");
+    if (opt.device < 0 || opt.device >= ndev) return fail(QTM_E_INVAL, "device %d not present", opt.device);
+    HIPCHECK(hipSetDevice(opt.device));
+    hipDeviceProp_t prop;
+    HIPCHECK(hipGetDeviceProperties(&prop, opt.device));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(QTM_E_DEVICE, "device %d is %s; this library is built for gfx950", opt.device, prop.gcnArchName);
+    qtm_ctx* c = new qtm_ctx();
+    c->o = opt;
+    c->device = opt.device;
+    c->stream = (hipStream_t)opt.stream;
+    c->ncu = prop.multiProcessorCount;
+    c->sys.resize(n_sys);
+    for (int s = 0; s < n_sys; ++s) {
+        int rc = setup_system(c->sys[s], sys[s], s, opt, allow_sparse);
+        if (rc) { qtm_destroy(c); return rc; }
+    }
+    if (hipMalloc(&c->d_sys, sizeof(qtm::DevSystem) * n_sys) != hipSuccess ||
+        hipMalloc(&c->d_fail, sizeof(long long)) != hipSuccess ||
+        hipMalloc(&c->d_counters, 4 * sizeof(unsigned long long)) != hipSuccess ||
+        hipMalloc(&c->d_cursor, sizeof(unsigned int)) != hipSuccess ||
+        hipMalloc(&c->d_mlp, sizeof(float) * qtm::kNTotal) != hipSuccess) {
+        qtm_destroy(c);
+        return fail(QTM_E_NOMEM, "device allocation failed");
+    }
+    if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+        qtm_destroy(c);
+        return fail(QTM_E_DEVICE, "hipEventCreate failed");
+    }
+    *out = c;
+    return QTM_OK;
+}
+
+int qtm_create(qtm_ctx** out, const qtm_op* H, const qtm_op* c_ops, int32_t n_c, const double* psi0,
+               const double* tlist, int32_t n_t, const qtm_op* e_ops, int32_t n_e, const qtm_opts* o) {
+    qtm_system s{H, c_ops, n_c, psi0, tlist, n_t, e_ops, n_e};
+    return create_common(out, 1, &s, o, true);
+}
+
+int qtm_create_batch(qtm_ctx** out, int32_t n_sys, const qtm_system* sys, const qtm_opts* o) {
+    if (n_sys < 1 || !sys) return fail(QTM_E_INVAL, "need n_sys >= 1 systems");
+    return create_common(out, n_sys, sys, o, false);
+}
+
+int qtm_run(qtm_ctx* ctx, int64_t ntraj, uint64_t seed) { return qtm_run_range(ctx, 0, ntraj, seed); }
+
+int qtm_run_range(qtm_ctx* c, int64_t traj_begin, int64_t count, uint64_t seed) {
+    if (check_ctx(c)) return QTM_E_INVAL;
+    if (count < 1 || traj_begin < 0) return fail(QTM_E_INVAL, "need count >= 1 and traj_begin >= 0");
+    if ((c->o.form & QTM_FORM_LEARNED) && !c->have_mlp) return fail(QTM_E_STATE, "learned form requested before qtm_set_proposal");
+    HIPCHECK(hipSetDevice(c->device));
+    auto t0 = std::chrono::steady_clock::now();
+    c->ran = false;
+    const int jcap = c->o.record_jumps, segc = c->o.seg_cap;
+    for (auto& S : c->sys) {
+        size_t m = (size_t)S.n_e * S.n_t;
+        int rc;
+        if ((rc = ensure_buf(S.X, sizeof(double2) * m * count))) return rc;
+        if ((rc = ensure_buf(S.tstat, sizeof(int) * 4 * count))) return rc;
+        if ((rc = ensure_buf(S.jn, sizeof(int) * count))) return rc;
+        if ((rc = ensure_buf(S.jt, sizeof(double) * (size_t)std::max(1, jcap) * (jcap ? count : 1)))) return rc;
+        if ((rc = ensure_buf(S.jc, sizeof(int) * (size_t)std::max(1, jcap) * (jcap ? count : 1)))) return rc;
+        if ((rc = ensure_buf(S.segs, sizeof(float) * qtm::kSegRec * (size_t)std::max(1, segc) * (segc ? count : 1)))) return rc;
+        if ((rc = ensure_buf(S.queue, sizeof(unsigned long long)))) return rc;
+        if ((rc = ensure_buf(S.sum, sizeof(double) * 2 * m))) return rc;
+        if ((rc = ensure_buf(S.sumsq, sizeof(double) * m))) return rc;
+        HIPCHECK(hipMemsetAsync(S.queue.p, 0, sizeof(unsigned long long), c->stream));
+        HIPCHECK(hipMemsetAsync(S.X.p, 0, sizeof(double2) * m * count, c->stream));
+        HIPCHECK(hipMemsetAsync(S.tstat.p, 0, sizeof(int) * 4 * count, c->stream));
+        if (segc) HIPCHECK(hipMemsetAsync(S.segs.p, 0, sizeof(float) * qtm::kSegRec * segc * count, c->stream));
+        S.dev.X = (double2*)S.X.p;
+        S.dev.tstat = (int*)S.tstat.p;
+        S.dev.jt = (double*)S.jt.p;
+        S.dev.jc = (int*)S.jc.p;
+        S.dev.jn = (int*)S.jn.p;
+        S.dev.segs = (float*)S.segs.p;
+        S.dev.queue = (unsigned long long*)S.queue.p;
+        S.dev.count = count;
+        S.dev.traj_begin = traj_begin;
+    }
+    std::vector<qtm::DevSystem> ds;
+    for (auto& S : c->sys) ds.push_back(S.dev);
+    HIPCHECK(hipMemcpyAsync(c->d_sys, ds.data(), sizeof(qtm::DevSystem) * ds.size(), hipMemcpyHostToDevice, c->stream));
+    long long fail_init = LLONG_MAX;
+    HIPCHECK(hipMemcpyAsync(c->d_fail, &fail_init, sizeof(long long), hipMemcpyHostToDevice, c->stream));
+    HIPCHECK(hipMemsetAsync(c->d_counters, 0, 4 * sizeof(unsigned long long), c->stream));
+    HIPCHECK(hipMemsetAsync(c->d_cursor, 0, sizeof(unsigned int), c->stream));
+
+    qtm::RunArgs a{};
+    a.sys = c->d_sys;
+    a.n_sys = (int)c->sys.size();
+    a.sys_cursor = c->d_cursor;
+    a.rtol = c->o.rtol;
+    a.atol = c->o.atol;
+    a.max_steps = c->o.max_steps;
+    a.seed = seed;
+    a.jcap = jcap;
+    a.seg_cap = segc;
+    a.learned = (c->o.form & QTM_FORM_LEARNED) ? 1 : 0;
+    a.mlp = c->d_mlp;
+    a.fail = c->d_fail;
+    a.counters = c->d_counters;
+    a.tile_cols = c->o.tile_cols;
+    a.persistent = (c->o.form & QTM_FORM_BATCHED) ? 1 : 0;
+    const SysHost& S0 = c->sys[0];
+    // failsafe bound on block cycles: every slot may run all its trajectories at max_steps
+    long long per_slot = count;   // worst case (one slot)
+    long long mc = (c->o.max_steps + 4) * 3;
+    a.max_cycles = (per_slot > 0 && mc < LLONG_MAX / (per_slot + 1)) ? mc * (per_slot + 1) : LLONG_MAX;
+
+    qtm::LaunchInfo li{};
+    HIPCHECK(hipEventRecord(c->ev0, c->stream));
+    int lr;
+    if (S0.sparse) {
+        int cols = c->o.tile_cols > 0 ? c->o.tile_cols : (c->o.precision == QTM_PREC_FP32 ? 4 : 2);
+        lr = qtm::launch_sparse(a, S0.dev, c->o.precision, cols, c->stream, &li);
+    } else {
+        int bpc = 0, lds = 0;
+        if (qtm::dense_occupancy(S0.d, c->o.precision, c->o.tile_cols, &bpc, &lds)) bpc = 1;
+        lr = qtm::launch_dense(a, S0.dev, S0.d, c->o.precision, bpc, c->stream, &li);
+    }
+    if (lr) return fail(QTM_E_DEVICE, "kernel launch failed (%d): %s", lr, hipGetErrorString(hipGetLastError()));
+    HIPCHECK(hipEventRecord(c->ev1, c->stream));
+    for (auto& S : c->sys)
+        if (qtm::launch_average(S.dev, (double*)S.sum.p, (double*)S.sumsq.p, c->stream))
+            return fail(QTM_E_DEVICE, "average kernel launch failed");
+    HIPCHECK(hipStreamSynchronize(c->stream));
+    float ms = 0.f;
+    HIPCHECK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    long long failv = 0;
+    unsigned long long ctrs[4];
+    HIPCHECK(hipMemcpy(&failv, c->d_fail, sizeof(long long), hipMemcpyDeviceToHost));
+    HIPCHECK(hipMemcpy(ctrs, c->d_counters, sizeof(ctrs), hipMemcpyDeviceToHost));
+    // statistics
+    qtm_stats_t st{};
+    st.ntraj = count;
+    for (auto& S : c->sys) {
+        std::vector<int> ts((size_t)4 * count);
+        HIPCHECK(hipMemcpy(ts.data(), S.tstat.p, sizeof(int) * 4 * count, hipMemcpyDeviceToHost));
+        for (long long q = 0; q < count; ++q) {
+            st.accepted += ts[4 * q]; st.rejected += ts[4 * q + 1]; st.segments += ts[4 * q + 2]; st.jumps += ts[4 * q + 3];
+        }
+        size_t m = (size_t)S.n_e * S.n_t;
+        S.h_sum.resize(2 * m);
+        S.h_sumsq.resize(m);
+        HIPCHECK(hipMemcpy(S.h_sum.data(), S.sum.p, sizeof(double) * 2 * m, hipMemcpyDeviceToHost));
+        HIPCHECK(hipMemcpy(S.h_sumsq.data(), S.sumsq.p, sizeof(double) * m, hipMemcpyDeviceToHost));
+        S.sum_count = count;
+    }
+    st.passes = (int64_t)ctrs[0];
+    st.rhs_evals = (int64_t)ctrs[0] * li.cols;
+    st.failed_traj = failv == LLONG_MAX ? -1 : failv;
+    st.kernel_ms = ms;
+    st.elapsed_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    st.blocks = li.blocks; st.threads = li.threads; st.tile_cols = li.cols; st.lds_bytes = li.lds;
+    c->st = st;
+    c->last_begin = traj_begin;
+    c->last_count = count;
+    if (failv != LLONG_MAX) return fail(QTM_E_STEP, "trajectory %lld failed (max_steps or step-size underflow)", failv);
+    c->ran = true;
+    return QTM_OK;
+}
+
+int qtm_sums(const qtm_ctx* c, int32_t s, double* sum, double* sumsq, int64_t* count) {
+    if (check_ctx(c)) return QTM_E_INVAL;
+    if (s < 0 || s >= (int)c->sys.size()) return fail(QTM_E_INVAL, "system index %d out of range", s);
+    if (!c->ran) return fail(QTM_E_STATE, "no successful run");
+    const SysHost& S = c->sys[s];
+    if (sum) std::memcpy(sum, S.h_sum.data(), sizeof(double) * S.h_sum.size());
+    if (sumsq) std::memcpy(sumsq, S.h_sumsq.data(), sizeof(double) * S.h_sumsq.size());
+    if (count) *count = S.sum_count;
+    return QTM_OK;
+}
+
+int qtm_expect_system(const qtm_ctx* c, int32_t s, double* mean, double* var) {
+    if (check_ctx(c)) return QTM_E_INVAL;
+    if (s < 0 || s >= (int)c->sys.size()) return fail(QTM_E_INVAL, "system index %d out of range", s);
+    if (!c->ran) return fail(QTM_E_STATE, "qtm_expect before a successful qtm_run");
+    if (!mean) return fail(QTM_E_INVAL, "null mean buffer");
+    const SysHost& S = c->sys[s];
+    size_t m = (size_t)S.n_e * S.n_t;
+    double n = (double)S.sum_count;
+    for (size_t i = 0; i < m; ++i) {
+        double mr = S.h_sum[2 * i] / n, mi = S.h_sum[2 * i + 1] / n;
+        mean[2 * i] = mr;
+        mean[2 * i + 1] = mi;
+        if (var) var[i] = std::max(0.0, S.h_sumsq[i] / n - mr * mr);
+    }
+    return QTM_OK;
+}
+
+int qtm_expect(const qtm_ctx* c, double* mean, double* var) { return qtm_expect_system(c, 0, mean, var); }
+
+int qtm_traj_expect(const qtm_ctx* c, int32_t s, double* X) {
+    if (check_ctx(c)) return QTM_E_INVAL;
+    if (s < 0 || s >= (int)c->sys.size()) return fail(QTM_E_INVAL, "system index %d out of range", s);
+    if (!c->ran) return fail(QTM_E_STATE, "no successful run");
+    if (!c->o.keep_traj) return fail(QTM_E_STATE, "context created without keep_traj");
+    const SysHost& S = c->sys[s];
+    HIPCHECK(hipMemcpy(X, S.X.p, sizeof(double2) * (size_t)S.n_e * S.n_t * c->last_count, hipMemcpyDeviceToHost));
+    return QTM_OK;
+}
+
+int qtm_jumps(const qtm_ctx* c, int32_t s, int64_t traj, int32_t cap, double* times, int32_t* channels, int32_t* count) {
+    if (check_ctx(c)) return QTM_E_INVAL;
+    if (s < 0 || s >= (int)c->sys.size()) return fail(QTM_E_INVAL, "system index %d out of range", s);
+    if (c->o.record_jumps <= 0) return fail(QTM_E_STATE, "context created without record_jumps");
+    if (!c->ran) return fail(QTM_E_STATE, "no successful run");
+    if (traj < 0 || traj >= c->last_count) return fail(QTM_E_INVAL, "trajectory %lld outside the last run", (long long)traj);
+    const SysHost& S = c->sys[s];
+    int n = 0;
+    HIPCHECK(hipMemcpy(&n, (int*)S.jn.p + traj, sizeof(int), hipMemcpyDeviceToHost));
+    if (count) *count = n;
+    int m = std::min(std::min(n, cap), c->o.record_jumps);
+    if (m > 0 && times) HIPCHECK(hipMemcpy(times, (double*)S.jt.p + (size_t)traj * c->o.record_jumps, sizeof(double) * m, hipMemcpyDeviceToHost));
+    if (m > 0 && channels) HIPCHECK(hipMemcpy(channels, (int*)S.jc.p + (size_t)traj * c->o.record_jumps, sizeof(int) * m, hipMemcpyDeviceToHost));
+    return QTM_OK;
+}
+
+int qtm_traj_stats(const qtm_ctx* c, int32_t s, int32_t* stats) {
+    if (check_ctx(c)) return QTM_E_INVAL;
+    if (s < 0 || s >= (int)c->sys.size()) return fail(QTM_E_INVAL, "system index %d out of range", s);
+    if (c->last_count == 0) return fail(QTM_E_STATE, "no run");
+    HIPCHECK(hipMemcpy(stats, c->sys[s].tstat.p, sizeof(int) * 4 * c->last_count, hipMemcpyDeviceToHost));
+    return QTM_OK;
+}
+
+int qtm_stats(const qtm_ctx* c, qtm_stats_t* st) {
+    if (check_ctx(c)) return QTM_E_INVAL;
+    if (!st) return fail(QTM_E_INVAL, "null stats");
+    *st = c->st;
+    return QTM_OK;
+}
+
+int qtm_segments(const qtm_ctx* c, float* out) {
+    if (check_ctx(c)) return QTM_E_INVAL;
+    if (c->o.seg_cap <= 0) return fail(QTM_E_STATE, "context created without seg_cap");
+    if (c->last_count == 0) return fail(QTM_E_STATE, "no run");
+    HIPCHECK(hipMemcpy(out, c->sys[0].segs.p, sizeof(float) * qtm::kSegRec * c->o.seg_cap * c->last_count, hipMemcpyDeviceToHost));
+    return QTM_OK;
+}
+
+int qtm_set_proposal(qtm_ctx* c, const float* params, int32_t n_params, const qtm_op* f_ops, int32_t n_f) {
+    if (check_ctx(c)) return QTM_E_INVAL;
+    if (!params || n_params != qtm::kNTotal) return fail(QTM_E_INVAL, "expected %d parameters", qtm::kNTotal);
+    if (n_f < 0 || n_f > 12) return fail(QTM_E_INVAL, "n_f must be in [0, 12]");
+    for (int i = 0; i < n_params; ++i) if (!std::isfinite(params[i])) return fail(QTM_E_INVAL, "non-finite parameter");
+    for (int i = qtm::kNParam + qtm::kNF; i < qtm::kNTotal; ++i)
+        if (!(params[i] > 0.f)) return fail(QTM_E_INVAL, "input scales must be positive");
+    HIPCHECK(hipSetDevice(c->device));
+    c->mlp_master.assign(params, params + n_params);
+    // weights (not biases, not the standardisation) rounded to BF16 for inference
+    std::vector<float> q;
+    working_copy(c->mlp_master, q);
+    HIPCHECK(hipMemcpy(c->d_mlp, q.data(), sizeof(float) * qtm::kNTotal, hipMemcpyHostToDevice));
+    for (auto& S : c->sys) {
+        const int d = S.d;
+        std::vector<double> fd((size_t)12 * d, 0.0);
+        for (int f = 0; f < n_f; ++f) {
+            if (f_ops[f].fmt != QTM_FMT_DIAG || f_ops[f].dim != d || !f_ops[f].val)
+                return fail(QTM_E_INVAL, "feature operator %d must be diagonal of dimension %d", f, d);
+            for (int i = 0; i < d; ++i) fd[(size_t)f * d + i] = f_ops[f].val[2 * i];
+        }
+        HIPCHECK(hipMemcpy((void*)S.dev.f_diag, fd.data(), sizeof(double) * fd.size(), hipMemcpyHostToDevice));
+        S.dev.n_f = n_f;
+    }
+    c->have_mlp = true;
+    return QTM_OK;
+}
+
+int qtm_get_proposal(const qtm_ctx* c, float* params, int32_t n_params) {
+    if (check_ctx(c)) return QTM_E_INVAL;
+    if (!c->have_mlp) return fail(QTM_E_STATE, "no proposal installed");
+    if (!params || n_params != qtm::kNTotal) return fail(QTM_E_INVAL, "expected %d parameters", qtm::kNTotal);
+    std::memcpy(params, c->mlp_master.data(), sizeof(float) * qtm::kNTotal);
+    return QTM_OK;
+}
+
+int qtm_proposal_grad(qtm_ctx* c, const float* feat, const float* tgt, int64_t n, float* loss, float* grad) {
+    if (check_ctx(c)) return QTM_E_INVAL;
+    if (!c->have_mlp) return fail(QTM_E_STATE, "no proposal installed");
+    if (!feat || !tgt || n < 1 || n > (1 << 24) || !grad) return fail(QTM_E_INVAL, "bad batch");
+    HIPCHECK(hipSetDevice(c->device));
+    DevScratch sc;
+    float *dF, *dT, *dP, *dPart, *dLp, *dG, *dL;
+    int nblk = qtm::mlp_partial_rows((int)n);
+    if (sc.get(&dF, n * qtm::kNF) || sc.get(&dT, n * 3) || sc.get(&dP, qtm::kNTotal) ||
+        sc.get(&dPart, (size_t)nblk * qtm::kNParam) || sc.get(&dLp, nblk) || sc.get(&dG, qtm::kNParam) || sc.get(&dL, 1))
+        return fail(QTM_E_NOMEM, "device allocation failed");
+    std::vector<float> q;
+    working_copy(c->mlp_master, q);
+    HIPCHECK(hipMemcpy(dF, feat, sizeof(float) * n * qtm::kNF, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(dT, tgt, sizeof(float) * n * 3, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(dP, q.data(), sizeof(float) * qtm::kNTotal, hipMemcpyHostToDevice));
+    if (qtm::launch_mlp_grad(dP, dF, dT, nullptr, 0, (int)n, dPart, dLp, dG, dL, c->stream))
+        return fail(QTM_E_DEVICE, "gradient kernel launch failed");
+    HIPCHECK(hipStreamSynchronize(c->stream));
+    HIPCHECK(hipMemcpy(grad, dG, sizeof(float) * qtm::kNParam, hipMemcpyDeviceToHost));
+    float l = 0.f;
+    HIPCHECK(hipMemcpy(&l, dL, sizeof(float), hipMemcpyDeviceToHost));
+    if (loss) *loss = l;
+    return QTM_OK;
+}
+
+int qtm_train_proposal(qtm_ctx* c, const float* feat, const float* tgt, int64_t n, int32_t n_epochs, int32_t batch,
+                       float lr, uint64_t shuffle_seed, float* loss_out) {
+    if (check_ctx(c)) return QTM_E_INVAL;
+    if (!feat || !tgt || n < 1 || n > (1LL << 30)) return fail(QTM_E_INVAL, "bad training set");
+    if (n_epochs < 1 || batch < 1 || !(lr > 0.f)) return fail(QTM_E_INVAL, "bad training options");
+    for (int64_t i = 0; i < n * qtm::kNF; ++i) if (!std::isfinite(feat[i])) return fail(QTM_E_INVAL, "non-finite feature");
+    for (int64_t i = 0; i < n * 3; ++i) if (!std::isfinite(tgt[i])) return fail(QTM_E_INVAL, "non-finite target");
+    HIPCHECK(hipSetDevice(c->device));
+    if (!c->have_mlp) {
+        init_proposal(c->mlp_master, feat, tgt, n, shuffle_seed);
+        c->have_mlp = true;
+    }
+    DevScratch sc;
+    float *dF, *dT, *dMaster, *dWork, *dM, *dV, *dPart, *dLp, *dG, *dL;
+    int* dPerm;
+    int nblk = qtm::mlp_partial_rows(batch);
+    if (sc.get(&dF, (size_t)n * qtm::kNF) || sc.get(&dT, (size_t)n * 3) || sc.get(&dMaster, qtm::kNTotal) ||
+        sc.get(&dWork, qtm::kNTotal) || sc.get(&dM, qtm::kNParam) || sc.get(&dV, qtm::kNParam) ||
+        sc.get(&dPart, (size_t)nblk * qtm::kNParam) || sc.get(&dLp, nblk) || sc.get(&dG, qtm::kNParam) ||
+        sc.get(&dL, 1) || sc.get(&dPerm, (size_t)n))
+        return fail(QTM_E_NOMEM, "device allocation failed");
+    std::vector<float> q;
+    working_copy(c->mlp_master, q);
+    HIPCHECK(hipMemcpy(dF, feat, sizeof(float) * n * qtm::kNF, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(dT, tgt, sizeof(float) * n * 3, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(dMaster, c->mlp_master.data(), sizeof(float) * qtm::kNTotal, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(dWork, q.data(), sizeof(float) * qtm::kNTotal, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemset(dM, 0, sizeof(float) * qtm::kNParam));
+    HIPCHECK(hipMemset(dV, 0, sizeof(float) * qtm::kNParam));
+    std::vector<int> perm(n);
+    uint64_t x = shuffle_seed * 0x9E3779B97F4A7C15ULL + 1;
+    auto next = [&]() { x ^= x << 13; x ^= x >> 7; x ^= x << 17; return x; };
+    int step = 0;
+    for (int ep = 0; ep < n_epochs; ++ep) {
+        for (int64_t i = 0; i < n; ++i) perm[i] = (int)i;
+        for (int64_t i = n - 1; i > 0; --i) std::swap(perm[i], perm[next() % (uint64_t)(i + 1)]);
+        HIPCHECK(hipMemcpy(dPerm, perm.data(), sizeof(int) * n, hipMemcpyHostToDevice));
+        double esum = 0.0;
+        int64_t eseen = 0;
+        for (int64_t b0 = 0; b0 + batch <= n || (b0 == 0 && n < batch); b0 += batch) {
+            int nb = (int)std::min<int64_t>(batch, n - b0);
+            if (qtm::launch_mlp_grad(dWork, dF, dT, dPerm, b0, nb, dPart, dLp, dG, dL, c->stream))
+                return fail(QTM_E_DEVICE, "gradient kernel launch failed");
+            if (qtm::launch_mlp_adam(dMaster, dWork, dG, dM, dV, lr, ++step, c->stream))
+                return fail(QTM_E_DEVICE, "adam kernel launch failed");
+            float l = 0.f;
+            HIPCHECK(hipMemcpyAsync(&l, dL, sizeof(float), hipMemcpyDeviceToHost, c->stream));
+            HIPCHECK(hipStreamSynchronize(c->stream));
+            esum += (double)l * nb;
+            eseen += nb;
+            if (n < batch) break;
+        }
+        if (loss_out) loss_out[ep] = (float)(esum / (double)std::max<int64_t>(1, eseen));
+    }
+    HIPCHECK(hipMemcpy(c->mlp_master.data(), dMaster, sizeof(float) * qtm::kNTotal, hipMemcpyDeviceToHost));
+    working_copy(c->mlp_master, q);
+    HIPCHECK(hipMemcpy(c->d_mlp, q.data(), sizeof(float) * qtm::kNTotal, hipMemcpyHostToDevice));
+    return QTM_OK;
+}
+
+void qtm_destroy(qtm_ctx* c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    for (auto& S : c->sys) {
+        for (auto& b : S.bufs) if (b.p) (void)hipFree(b.p);
+        free_buf(S.X); free_buf(S.tstat); free_buf(S.jt); free_buf(S.jc); free_buf(S.jn);
+        free_buf(S.segs); free_buf(S.queue); free_buf(S.sum); free_buf(S.sumsq);
+    }
+    if (c->d_sys) (void)hipFree(c->d_sys);
+    if (c->d_fail) (void)hipFree(c->d_fail);
+    if (c->d_counters) (void)hipFree(c->d_counters);
+    if (c->d_cursor) (void)hipFree(c->d_cursor);
+    if (c->d_mlp) (void)hipFree(c->d_mlp);
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,139 @@
+// qtm_dense.hip -- trajectory kernel for dense H_eff: the product K = M W of a
+// 16-column block is a real-embedded GEMM on the FP64 or FP32 matrix cores with
+// the operand block staged in LDS; plus the index-ordered averaging kernel.
+#include "qtm_body.h"
+
+namespace qtm {
+
+template <int T, int PREC>
+__global__ void __launch_bounds__(512) traj_dense_kernel(RunArgs a, int lds_m) {
+    extern __shared__ double smem[];
+    __shared__ int flags[8];
+    typedef typename MfmaT<PREC>::in_t in_t;
+    const DevSystem& S = a.sys[0];
+    DenseLayout<T, PREC> L;
+    L.S = &S;
+    L.lane = threadIdx.x & 63; L.w = threadIdx.x >> 6; L.lg = L.lane >> 4; L.c16 = L.lane & 15;
+    const int NW = blockDim.x >> 6;
+    L.RT = S.rt; L.dp = S.dp; L.d = S.d; L.KB = 2 * S.dp / 4;
+    L.wpc = (L.RT + T - 1) / T;
+    L.nct = a.tile_cols / 16;                 // set by the launcher; NW == wpc * nct
+    L.NB = 16 * L.nct;
+    L.ct = L.w / L.wpc; L.rg = L.w % L.wpc;
+    L.active = L.ct < L.nct;
+    // LDS carve-up: [column states][M fragments if lds_m][W staging][reduction]
+    char* p = (char*)smem;
+    Col* cs = (Col*)p;
+    p += ((size_t)L.NB * sizeof(Col) + 15) & ~(size_t)15;
+    size_t msz = (size_t)(2 * S.dp) * (2 * S.dp) * sizeof(in_t);
+    if (lds_m) {
+        in_t* Ml = (in_t*)p;
+        const in_t* Mg = MfmaT<PREC>::frag(S);
+        for (size_t i = threadIdx.x; i < msz / sizeof(in_t); i += blockDim.x) Ml[i] = Mg[i];
+        L.Mf = Ml;
+        p += (msz + 15) & ~(size_t)15;
+    } else {
+        L.Mf = MfmaT<PREC>::frag(S);
+    }
+    size_t wsz = (size_t)L.nct * 2 * S.dp * 16 * sizeof(double);   // also holds [dp][NB] double2
+    L.Wb = (in_t*)p;
+    L.Stage = (double2*)p;
+    p += wsz;
+    L.red = (double*)p;
+    __syncthreads();
+    Body<DenseLayout<T, PREC>> B(L, S, a, cs, flags);
+    B.run();
+}
+
+// Trajectory average in index order: one thread per (observable, time).
+__global__ void average_kernel(const double2* X, long long count, int m, double* sum, double* sumsq) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    double sr = 0.0, si = 0.0, s2 = 0.0;
+    for (long long q = 0; q < count; ++q) {
+        double2 x = X[q * m + i];
+        sr += x.x; si += x.y; s2 += x.x * x.x;
+    }
+    sum[2 * i] = sr; sum[2 * i + 1] = si; sumsq[i] = s2;
+}
+
+// ------------------------------------------------------------------ host launchers
+static size_t dense_lds(int max_dp, int prec, int waves, int lds_m, int nct) {
+    size_t es = prec == 0 ? 8 : 4;
+    size_t cols = (((size_t)16 * nct * sizeof(Col)) + 15) & ~(size_t)15;
+    size_t m = lds_m ? (((size_t)(2 * max_dp) * (2 * max_dp) * es + 15) & ~(size_t)15) : 0;
+    size_t wsz = (size_t)nct * 2 * max_dp * 16 * sizeof(double);
+    size_t red = (size_t)waves * 16 * kNVMax * sizeof(double);
+    return cols + m + wsz + red;
+}
+
+template <int T, int PREC> static const void* dense_fn() { return (const void*)&traj_dense_kernel<T, PREC>; }
+
+// Block geometry of the dense kernel for dimension d: T row tiles per wave,
+// wpc waves per 16-column tile, nct column tiles (at most 8 waves per block).
+static int dense_geometry(int d, int tile_cols, int* T, int* wpc, int* nct, int* dp) {
+    *dp = (d + 7) / 8 * 8;
+    int rt = 2 * *dp / 16;
+    if (rt > 16) return -1;
+    *T = rt <= 8 ? 1 : 2;
+    *wpc = (rt + *T - 1) / *T;
+    int maxct = 8 / *wpc;
+    int want = tile_cols > 0 ? tile_cols / 16 : 1;
+    *nct = std::max(1, std::min(maxct, want));
+    return 0;
+}
+
+static const void* dense_kernel_fn(int T, int prec) {
+    return T == 1 ? (prec == 0 ? dense_fn<1, 0>() : dense_fn<1, 1>()) : (prec == 0 ? dense_fn<2, 0>() : dense_fn<2, 1>());
+}
+
+int dense_occupancy(int max_d, int prec, int tile_cols, int* blocks_per_cu, int* lds) {
+    int T, wpc, nct, dp;
+    if (dense_geometry(max_d, tile_cols, &T, &wpc, &nct, &dp)) return -1;
+    size_t es = prec == 0 ? 8 : 4;
+    int lds_m = (size_t)(2 * dp) * (2 * dp) * es <= 56 * 1024;
+    int waves = wpc * nct;
+    size_t l = dense_lds(dp, prec, waves, lds_m, nct);
+    const void* fn = dense_kernel_fn(T, prec);
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l) != hipSuccess) return -2;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, waves * 64, l) != hipSuccess) return -2;
+    *blocks_per_cu = nb;
+    *lds = (int)l;
+    return 0;
+}
+
+int launch_dense(const RunArgs& a, const DevSystem& s0, int max_d, int prec, int blocks_per_cu,
+                 hipStream_t st, LaunchInfo* info) {
+    int T, wpc, nct, dp;
+    if (dense_geometry(max_d, a.tile_cols, &T, &wpc, &nct, &dp)) return -1;
+    int waves = wpc * nct;
+    size_t es = prec == 0 ? 8 : 4;
+    int lds_m = (size_t)(2 * dp) * (2 * dp) * es <= 56 * 1024;
+    size_t lds = dense_lds(dp, prec, waves, lds_m, nct);
+    int cols = 16 * nct;
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return -3;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return -3;
+    long long need = (s0.count + cols - 1) / cols;
+    long long blocks = a.persistent ? (long long)ncu * (blocks_per_cu > 0 ? blocks_per_cu : 1) : need;
+    if (blocks > need) blocks = need;
+    if (blocks < 1) blocks = 1;
+    const void* fn = dense_kernel_fn(T, prec);
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) return -3;
+    RunArgs aa = a;
+    aa.tile_cols = cols;
+    int lm = lds_m;
+    void* args[] = {(void*)&aa, (void*)&lm};
+    if (hipLaunchKernel(fn, dim3((unsigned)blocks), dim3(waves * 64), args, lds, st) != hipSuccess) return -3;
+    if (info) { info->blocks = (int)blocks; info->threads = waves * 64; info->lds = (int)lds; info->cols = cols; }
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int launch_average(const DevSystem& s, double* sum, double* sumsq, hipStream_t st) {
+    int m = s.n_e * s.n_t;
+    hipLaunchKernelGGL(average_kernel, dim3((m + 255) / 256), dim3(256), 0, st, (const double2*)s.X, s.count, m, sum, sumsq);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+}  // namespace qtm

@@ -1,0 +1,94 @@
+// qtm_internal.h -- device-side data structures shared by the host runtime and
+// the HIP kernels of libqtm (not part of the public ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qtm {
+
+constexpr int kMaxE = 16;        // expectation operators per system
+constexpr int kMaxC = 16;        // collapse operators per system
+constexpr int kNVMax = 16;       // values per column in one block reduction
+constexpr int kNF = 16, kNH = 64, kNO = 3;   // proposal network 16 -> 64 -> 64 -> 3
+constexpr int kNParam = kNH * kNF + kNH + kNH * kNH + kNH + kNO * kNH + kNO;  // 5443
+constexpr int kNTotal = kNParam + 2 * kNF;                                      // + mean, scale
+constexpr int kSegRec = 20;      // floats per segment record
+
+// Column (trajectory slot) states.
+enum : int { ST_EMPTY = 0, ST_NEW = 1, ST_NEEDK1 = 2, ST_NEEDF1 = 3, ST_PROBED = 4, ST_STEP = 5 };
+// Post-step actions.
+enum : int { ACT_NONE = 0, ACT_REJECT = 1, ACT_ACCEPT = 2, ACT_JUMP = 3, ACT_FAIL = 4, ACT_POSTJUMP = 5 };
+
+// One system as the kernels see it.
+struct DevSystem {
+    int d, dp;                 // dimension; dense kernels pad it to a multiple of 8
+    int n_c, n_e, n_t, n_f;
+    int rt;                    // dense: 16-row tiles of the real-embedded operator (2dp/16)
+    int any_csr_e;             // some observable needs the staged-vector product
+    int e_nv[kMaxE];           // values per observable (1: real diagonal, 2: complex)
+    int e_fmt[kMaxE];          // 1 CSR, 2 diagonal
+    int e_doff[kMaxE];         // diagonal values offset into e_val
+    // right-hand-side operator M = -i H_eff
+    const double* Mfrag;       // dense: (2dp)^2 doubles in MFMA A-fragment order
+    const float* Mfrag32;      // same, rounded to FP32
+    const int* sl_off;         // sparse: sliced ELL, 64-row slices; entry offset of each slice
+    const int* sl_w;           // width of each slice
+    const int* sl_col;         // [slice entries], column-major inside a slice
+    const double2* sl_val;
+    const float2* sl_val32;
+    // collapse operators (CSR, concatenated; row pointers absolute)
+    const int* c_rp;           // [n_c][d+1]
+    const int* c_ci;
+    const double2* c_val;
+    // observables (CSR part: absolute row pointers [n_e][d+1]; diagonal part in e_val)
+    const int* e_rp;
+    const int* e_ci;
+    const double2* e_val;
+    const double* f_diag;      // [12][d] diagonal feature operators (learned form)
+    const double2* psi0;       // [d]
+    const double* tlist;       // [n_t]
+    double t0, tend;
+    // per-run outputs (indices relative to traj_begin)
+    double2* X;                // [count][n_e][n_t]
+    int* tstat;                // [count][4] accepted, rejected, segments, jumps
+    double* jt;                // [count][jcap]
+    int* jc;                   // [count][jcap]
+    int* jn;                   // [count]
+    float* segs;               // [count][seg_cap][kSegRec]
+    unsigned long long* queue; // next relative trajectory index to hand out
+    long long count;
+    long long traj_begin;
+    unsigned long long key1;   // Philox key word 1 (system index)
+};
+
+struct RunArgs {
+    const DevSystem* sys;      // device array of systems handled by this launch
+    int n_sys;
+    unsigned int* sys_cursor;  // first system that may still have trajectories
+    double rtol, atol;
+    long long max_steps;
+    unsigned long long seed;
+    int jcap, seg_cap;
+    int learned;
+    const float* mlp;          // [kNTotal] weights (BF16-rounded values), biases, mean, scale
+    long long* fail;           // smallest failing global trajectory index (LLONG_MAX: none)
+    unsigned long long* counters;  // [4]: passes, rhs column-evaluations, cycles, unused
+    long long max_cycles;      // failsafe bound on block cycles
+    int tile_cols;             // requested columns per block (0: as many as the waves allow)
+    int persistent;            // refill free slots from the queue
+};
+
+// Host-side launchers (defined in qtm_kernels.hip).
+struct LaunchInfo { int blocks, threads, lds, cols; };
+int launch_dense(const RunArgs& a, const DevSystem& s0, int max_d, int prec, int blocks_per_cu,
+                 hipStream_t st, LaunchInfo* info);
+int launch_sparse(const RunArgs& a, const DevSystem& s0, int prec, int cols, hipStream_t st, LaunchInfo* info);
+int launch_average(const DevSystem& s, double* sum, double* sumsq, hipStream_t st);
+int dense_occupancy(int max_d, int prec, int tile_cols, int* blocks_per_cu, int* lds);
+// proposal network (qtm_mlp.hip)
+int launch_mlp_grad(const float* P, const float* feat, const float* tgt, const int* perm, long long base, int n,
+                    float* partial, float* loss_part, float* grad, float* loss, hipStream_t st);
+int launch_mlp_adam(float* master, float* work, const float* grad, float* m, float* v, float lr, int step, hipStream_t st);
+int mlp_partial_rows(int n);
+
+}  // namespace qtm

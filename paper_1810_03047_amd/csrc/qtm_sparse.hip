@@ -1,0 +1,61 @@
+// qtm_sparse.hip -- trajectory kernel for sparse H_eff: sliced-ELL SpMM, one
+// thread per state component, the column block staged in LDS.
+#include "qtm_body.h"
+
+namespace qtm {
+
+template <int RPT, int NBC, int PREC>
+__global__ void __launch_bounds__(1024) traj_sparse_kernel(RunArgs a) {
+    extern __shared__ double smem[];
+    __shared__ int flags[8];
+    const DevSystem& S = a.sys[0];
+    SparseLayout<RPT, NBC, PREC> L;
+    L.S = &S;
+    L.tid = threadIdx.x; L.nthr = blockDim.x; L.lane = threadIdx.x & 63; L.w = threadIdx.x >> 6;
+    L.NW = blockDim.x >> 6; L.d = S.d; L.NB = NBC; L.dp = S.d;
+    char* p = (char*)smem;
+    Col* cs = (Col*)p;
+    p += ((size_t)NBC * sizeof(Col) + 15) & ~(size_t)15;
+    size_t ssz = (size_t)S.d * NBC * sizeof(double2);
+    L.Stage = (double2*)p;
+    L.Stage32 = (float2*)p;
+    p += ssz;
+    L.red = (double*)p;
+    Body<SparseLayout<RPT, NBC, PREC>> B(L, S, a, cs, flags);
+    B.run();
+}
+
+int launch_sparse(const RunArgs& a, const DevSystem& s0, int prec, int cols, hipStream_t st, LaunchInfo* info) {
+    int threads = s0.d >= 1024 ? 1024 : ((s0.d + 63) / 64) * 64;
+    int rpt = (s0.d + threads - 1) / threads;
+    if (rpt > 2) return -1;
+    if (cols != 1 && cols != 2 && cols != 4) cols = 2;
+    size_t lds = (((size_t)cols * sizeof(Col) + 15) & ~(size_t)15) + (size_t)s0.d * cols * sizeof(double2) +
+                 (size_t)(threads / 64) * cols * kNVMax * sizeof(double);
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return -3;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return -3;
+    const void* fn = nullptr;
+#define QTM_SPARSE_CASE(R, C, P) \
+    if (rpt == R && cols == C && prec == P) fn = (const void*)&traj_sparse_kernel<R, C, P>;
+    QTM_SPARSE_CASE(1, 1, 0) QTM_SPARSE_CASE(1, 2, 0) QTM_SPARSE_CASE(1, 4, 0)
+    QTM_SPARSE_CASE(1, 1, 1) QTM_SPARSE_CASE(1, 2, 1) QTM_SPARSE_CASE(1, 4, 1)
+    QTM_SPARSE_CASE(2, 1, 0) QTM_SPARSE_CASE(2, 2, 0) QTM_SPARSE_CASE(2, 4, 0)
+    QTM_SPARSE_CASE(2, 1, 1) QTM_SPARSE_CASE(2, 2, 1) QTM_SPARSE_CASE(2, 4, 1)
+#undef QTM_SPARSE_CASE
+    if (!fn) return -1;
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) return -3;
+    int nb = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, threads, lds) != hipSuccess) nb = 1;
+    if (nb < 1) nb = 1;
+    long long need = (s0.count + cols - 1) / cols;
+    long long blocks = a.persistent ? (long long)ncu * nb : need;
+    if (blocks > need) blocks = need;
+    if (blocks < 1) blocks = 1;
+    void* args[] = {(void*)&a};
+    if (hipLaunchKernel(fn, dim3((unsigned)blocks), dim3(threads), args, lds, st) != hipSuccess) return -3;
+    if (info) { info->blocks = (int)blocks; info->threads = threads; info->lds = (int)lds; info->cols = cols; }
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+}  // namespace qtm
