@@ -87,8 +87,10 @@ typedef struct {
     void* stream;             /* hipStream_t to run on, NULL: the null stream */
     int32_t keep_traj;        /* keep per-trajectory expectation values (qtm_traj_expect) */
     int32_t seg_cap;          /* segment records per trajectory for proposal training (0: off) */
-    int32_t tile_cols;        /* 0: autotuned; else columns (trajectories) per workgroup */
-    int32_t reserved[7];
+    int32_t tile_cols;        /* sparse and large dense kernels: trajectories per workgroup (0: default) */
+    int32_t team_waves;       /* small dense kernel (d <= 64): wavefronts per 16-trajectory team,
+                                 one of qtm_tile_candidates() (0: default shape) */
+    int32_t reserved[6];
 } qtm_opts;
 
 /* Per-run statistics (summed over trajectories of the last qtm_run). */
@@ -224,6 +226,11 @@ int qtm_train_proposal(qtm_ctx* ctx, const float* feat, const float* tgt, int64_
  * computed by the device forward and backward kernels (BF16 weights, FP32
  * activations): grad receives QTM_MLP_NPARAM floats (host). */
 int qtm_proposal_grad(qtm_ctx* ctx, const float* feat, const float* tgt, int64_t n, float* loss, float* grad);
+
+/* Team sizes (wavefronts per 16-trajectory team) the small dense kernel offers
+ * for dimension d, written to waves[0..return-1] (at most cap); the first one
+ * is the default.  Used by autotuners; returns 0 when d > 64.  Not a status. */
+int qtm_tile_candidates(int32_t d, int32_t* waves, int32_t cap);
 
 /* ----------------------------------------------------------- misc */
 /* Message of the last failing call in this thread ("" if none).  Not an int. */

@@ -434,9 +434,11 @@ void features(const Problem& P, const cd* y, double r, double t, double* f, std:
 }
 
 double snap_step(double log_h) {
-    // h = 2^(round(4 log2 h)/4)
-    double l2 = log_h / std::log(2.0);
-    return std::exp2(std::nearbyint(4.0 * l2) / 4.0);
+    // h = 2^(k/4) with k = round(4 log2 h), evaluated exactly as 2^floor(k/4) * 2^((k mod 4)/4)
+    const double quarter[4] = {1.0, 1.18920711500272106672, 1.41421356237309504880, 1.68179283050742908606};
+    long k = std::lrint(4.0 * (log_h / std::log(2.0)));
+    long q = k >= 0 ? k / 4 : -((-k + 3) / 4);
+    return std::ldexp(quarter[k - 4 * q], (int)q);
 }
 
 /* Segment record for training data: features, realised jump delay (or censored),

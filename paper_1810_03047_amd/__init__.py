@@ -48,7 +48,7 @@ class _Opts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("precision", C.c_int32), ("form", C.c_uint32),
                 ("max_steps", C.c_int64), ("device", C.c_int32), ("record_jumps", C.c_int32),
                 ("stream", C.c_void_p), ("keep_traj", C.c_int32), ("seg_cap", C.c_int32),
-                ("tile_cols", C.c_int32), ("reserved", C.c_int32 * 7)]
+                ("tile_cols", C.c_int32), ("team_waves", C.c_int32), ("reserved", C.c_int32 * 6)]
 
 
 class _Stats(C.Structure):
@@ -85,9 +85,17 @@ _SIGS = {
     "qtm_segments": (C.c_int, [C.c_void_p, _fp]),
     "qtm_train_proposal": (C.c_int, [C.c_void_p, _fp, _fp, C.c_int64, C.c_int32, C.c_int32, C.c_float, C.c_uint64, _fp]),
     "qtm_proposal_grad": (C.c_int, [C.c_void_p, _fp, _fp, C.c_int64, _fp, _fp]),
+    "qtm_tile_candidates": (C.c_int, [C.c_int32, _ip, C.c_int32]),
     "qtm_last_error": (C.c_char_p, []),
     "qtm_destroy": (None, [C.c_void_p]),
 }
+
+
+def tile_candidates(d: int):
+    """Team sizes the small dense kernel offers for dimension d (first = default)."""
+    w = np.zeros(8, dtype=np.int32)
+    n = load().qtm_tile_candidates(int(d), _ptr(w, _ip), 8)
+    return [int(x) for x in w[:n]]
 
 
 def exported_names():
@@ -153,6 +161,7 @@ class Opts:
     keep_traj: int = 0
     seg_cap: int = 0
     tile_cols: int = 0
+    team_waves: int = 0
     stream: Optional[int] = None      # raw hipStream_t; None: torch's current stream when available
 
     def _c(self) -> _Opts:
@@ -161,6 +170,7 @@ class Opts:
         o.rtol, o.atol, o.precision, o.form = self.rtol, self.atol, self.precision, self.form
         o.max_steps, o.device, o.record_jumps = self.max_steps, self.device, self.record_jumps
         o.keep_traj, o.seg_cap, o.tile_cols = self.keep_traj, self.seg_cap, self.tile_cols
+        o.team_waves = self.team_waves
         st = self.stream
         if st is None:
             try:

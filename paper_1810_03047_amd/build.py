@@ -17,8 +17,11 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libqtm.so")
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = ["qtm_dense.hip", "qtm_sparse.hip", "qtm_mlp.hip", "qtm_capi.cpp"]
 ARCH = "gfx950"
+# team-kernel shapes (row tiles per wave x waves per team), one translation unit each
+TEAM_SHAPES = ("1x1", "2x1", "1x2", "1x3", "1x4", "2x2", "1x5", "3x2", "5x1", "1x6", "2x3", "1x7", "4x2", "1x8", "2x4")
+SOURCES = ["qtm_wave.hip"] + [f"qtm_wave_t{s}.hip" for s in TEAM_SHAPES] + ["qtm_dense.hip", "qtm_sparse.hip",
+                                                                     "qtm_mlp.hip", "qtm_capi.cpp"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-Wno-unused-result"]
@@ -39,7 +42,7 @@ def _compile(src: str, verbose: bool) -> str:
     return obj
 
 
-def build(verbose: bool = False, jobs: int = 4) -> str:
+def build(verbose: bool = False, jobs: int = 8) -> str:
     os.makedirs(OBJDIR, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
@@ -53,7 +56,7 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--jobs", type=int, default=4)
+    ap.add_argument("--jobs", type=int, default=8)
     ap.add_argument("-v", "--verbose", action="store_true")
     a = ap.parse_args(argv)
     print(build(a.verbose, a.jobs))

@@ -75,6 +75,25 @@ __device__ __forceinline__ void philox4x64(uint64_t c[4], uint64_t k0, uint64_t 
 }
 __device__ __forceinline__ double u53(uint64_t x) { return ((double)(x >> 11) + 0.5) * 0x1.0p-53; }
 
+// x^(-1/5) for x > 0: FP32 seed, then two Newton steps on g^5 x = 1 in FP64
+// (relative error ~1e-16; far cheaper in registers than the double-double pow).
+__device__ __forceinline__ double inv_fifth_root(double x) {
+    double g = (double)exp2f(-0.2f * log2f((float)x));
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        double g2 = g * g;
+        double e = 1.0 - x * (g2 * g2 * g);        // residual of g^5 x = 1
+        g = fma(g, 0.2 * e, g);                      // g (1 + e/5)
+    }
+    return g;
+}
+// 2^(k/4) for integer k, exactly: 2^floor(k/4) times a correctly rounded 2^(m/4)
+__device__ __forceinline__ double exp2_quarter(int k) {
+    const double f[4] = {1.0, 1.18920711500272106672, 1.41421356237309504880, 1.68179283050742908606};
+    int q = k >> 2;                                   // floor division
+    return ldexp(f[k & 3], q);
+}
+
 // ------------------------------------------------------------------ complex
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
@@ -329,7 +348,7 @@ template <int RPT, int NBC, int PREC> struct SparseLayout {
 __device__ __forceinline__ float gelu_f(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
 
 // FP32 accumulation on BF16-valued weights; one thread.
-__device__ __noinline__ float mlp_logh(const float* P, const float* f) {
+static __device__ __noinline__ float mlp_logh(const float* P, const float* f) {
     const float* W1 = P;
     const float* b1 = W1 + kNH * kNF;
     const float* W2 = b1 + kNH;
@@ -366,6 +385,7 @@ struct Body {
     Col* cs;
     int* flags;
 
+    unsigned long long passes = 0;   // product passes of this block (thread 0), added once at exit
     // vectors (registers): state and step result in FP64, stage derivatives in the product precision
     typedef typename L::kv_t kv_t;
     double2 y[L::NE], yn[L::NE];
@@ -621,7 +641,7 @@ struct Body {
         const int tid = threadIdx.x;
         kv_t K[L::NE];
         Ly.rhs(y, K);
-        if (tid == 0) atomicAdd(&A.counters[0], 1ULL);
+        if (tid == 0) ++passes;
 #pragma unroll
         for (int e = 0; e < L::NE; ++e) {
             int gc = Ly.gcol(Ly.slot(e));
@@ -661,13 +681,12 @@ struct Body {
                     double nn = Ly.red_sum(tid, 14);
 #pragma unroll
                     for (int v = 0; v < 14; ++v) f[v] = (float)(Ly.red_sum(tid, v) / nn);
-                    f[14] = (float)log(c.r);
+                    f[14] = logf((float)c.r);
                     f[15] = (float)((c.t - S.t0) / (S.tend - S.t0));
                     if (A.learned) {
                         float lh = mlp_logh(A.mlp, f);
                         // snap to the grid 2^(k/4): h = 2^(round(4 log2 h)/4)
-                        double l2 = (double)lh / 0.69314718055994530942;
-                        double h = exp2(rint(4.0 * l2) / 4.0);
+                        double h = exp2_quarter((int)rint(4.0 * ((double)lh / 0.69314718055994530942)));
                         c.h = fmin(h, S.tend - c.t);
                         c.state = ST_STEP;
                     }
@@ -731,7 +750,7 @@ struct Body {
             if (s == 6) yn[e] = acc;
         }
         Ly.rhs(W, k[s]);
-        if (threadIdx.x == 0) atomicAdd(&A.counters[0], 1ULL);
+        if (threadIdx.x == 0) ++passes;
     }
 
     QTM_DI void stages() {
@@ -759,7 +778,7 @@ struct Body {
                 if (c.state == ST_NEEDF1) {
                     double d2 = sqrt(Ly.red_sum(tid, 0) / S.d) / c.h0;
                     double h1 = (c.d1 <= 1e-15 && d2 <= 1e-15) ? fmax(1e-6, c.h0 * 1e-3)
-                                                               : pow(0.01 / fmax(c.d1, d2), 0.2);
+                                                               : 1.0 / inv_fifth_root(0.01 / fmax(c.d1, d2));
                     c.h = fmin(fmin(100.0 * c.h0, h1), S.tend - c.t);
                     c.state = ST_PROBED;
                 }
@@ -807,7 +826,7 @@ struct Body {
                 double err = sqrt(Ly.red_sum(tid, 0) / S.d);
                 c.n2 = Ly.red_sum(tid, 1);
                 if (!(err <= 1.0)) {
-                    double f = isfinite(err) ? fmax(0.2, 0.9 * pow(err, -0.2)) : 0.2;
+                    double f = isfinite(err) ? fmax(0.2, 0.9 * inv_fifth_root(err)) : 0.2;
                     c.h *= f;
                     c.rejected = 1;
                     c.nrej++;
@@ -815,7 +834,7 @@ struct Body {
                     if (!(c.h > 16.0 * DBL_EPSILON * fabs(c.t)) || c.natt >= A.max_steps) c.action = ACT_FAIL;
                 } else {
                     c.nacc++;
-                    double fac = (err == 0.0) ? 10.0 : fmin(10.0, 0.9 * pow(err, -0.2));
+                    double fac = (err == 0.0) ? 10.0 : fmin(10.0, 0.9 * inv_fifth_root(err));
                     if (c.rejected) fac = fmin(1.0, fac);
                     c.fac = fac;
                     if (A.seg_cap > 0 && c.first_acc && c.seg_rec < A.seg_cap) {

@@ -168,6 +168,33 @@ std::vector<T> build_frag(const HCsr& M, int dp, int prec) {
     return f;
 }
 
+// Complex-compressed operator of the team kernel (see its product()):
+// FP64: entry [(rt * dp/4 + kp) * 32 + ql * 4 + jl] = M[8 rt + ql][4 kp + jl]
+// FP32: entry [(rt * dp/2 + kb) * 16 + ql * 2 + jl] = M[8 rt + ql][2 kb + jl]
+template <class T>
+std::vector<T> build_compressed(const HCsr& M, int dp, int prec) {
+    std::vector<cd> Md((size_t)dp * dp, 0.0);
+    for (int i = 0; i < M.d; ++i)
+        for (int p = M.rp[i]; p < M.rp[i + 1]; ++p) Md[(size_t)i * dp + M.ci[p]] += M.v[p];
+    const int RT = dp / 8;
+    std::vector<T> out((size_t)2 * dp * dp);
+    auto put = [&](size_t idx, cd z) { out[2 * idx] = (T)z.real(); out[2 * idx + 1] = (T)z.imag(); };
+    if (prec == 0) {
+        for (int rt = 0; rt < RT; ++rt)
+            for (int kp = 0; kp < dp / 4; ++kp)
+                for (int ql = 0; ql < 8; ++ql)
+                    for (int jl = 0; jl < 4; ++jl)
+                        put(((size_t)rt * (dp / 4) + kp) * 32 + ql * 4 + jl, Md[(size_t)(8 * rt + ql) * dp + 4 * kp + jl]);
+    } else {
+        for (int rt = 0; rt < RT; ++rt)
+            for (int kb = 0; kb < dp / 2; ++kb)
+                for (int ql = 0; ql < 8; ++ql)
+                    for (int jl = 0; jl < 2; ++jl)
+                        put(((size_t)rt * (dp / 2) + kb) * 16 + ql * 2 + jl, Md[(size_t)(8 * rt + ql) * dp + 2 * kb + jl]);
+    }
+    return out;
+}
+
 struct DevBuf {
     void* p = nullptr;
     size_t n = 0;
@@ -285,6 +312,8 @@ int setup_system(SysHost& S, const qtm_system& in, int idx, const qtm_opts& o, b
         D.rt = 2 * dp / 16;
         if ((rc = upload(S, &D.Mfrag, build_frag<double>(M, dp, 0)))) return rc;
         if ((rc = upload(S, &D.Mfrag32, build_frag<float>(M, dp, 1)))) return rc;
+        if ((rc = upload(S, &D.Mc64, build_compressed<double>(M, dp, 0)))) return rc;
+        if ((rc = upload(S, &D.Mc32, build_compressed<float>(M, dp, 1)))) return rc;
     } else {
         D.dp = d;
         int nsl = (d + 63) / 64;
@@ -473,6 +502,15 @@ void qtm_opts_default(qtm_opts* o) {
 
 const char* qtm_last_error(void) { return g_err.c_str(); }
 
+int qtm_tile_candidates(int32_t d, int32_t* waves, int32_t cap) {
+    if (!waves || cap < 1) return 0;
+    int tmp[8];
+    int n = qtm::team_candidates(d, tmp, 8);
+    n = std::min(n, (int)cap);
+    for (int i = 0; i < n; ++i) waves[i] = tmp[i];
+    return n;
+}
+
 static int create_common(qtm_ctx** out, int32_t n_sys, const qtm_system* sys, const qtm_opts* o, bool allow_sparse) {
     if (!out) return fail(QTM_E_INVAL, "null output pointer");
     *out = nullptr;
@@ -483,8 +521,10 @@ static int create_common(qtm_ctx** out, int32_t n_sys, const qtm_system* sys, co
     if (opt.precision != QTM_PREC_FP64 && opt.precision != QTM_PREC_FP32) return fail(QTM_E_INVAL, "unknown precision %d", opt.precision);
     if (opt.max_steps < 1) return fail(QTM_E_INVAL, "max_steps must be >= 1");
     if (opt.record_jumps < 0 || opt.seg_cap < 0) return fail(QTM_E_INVAL, "negative capacity");
+    if (opt.team_waves < 0 || opt.tile_cols < 0) return fail(QTM_E_INVAL, "negative tile option");
     int ndev = 0;
-    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(QTM_E_DEVICE, "no HIP device");
+    hipError_t de = hipGetDeviceCount(&ndev);
+    if (de != hipSuccess || ndev < 1) return fail(QTM_E_DEVICE, "no HIP device (%s, count %d)", hipGetErrorString(de), ndev);
     if (opt.device < 0 || opt.device >= ndev) return fail(QTM_E_INVAL, "device %d not present", opt.device);
     HIPCHECK(hipSetDevice(opt.device));
     hipDeviceProp_t prop;
@@ -601,9 +641,14 @@ int qtm_run_range(qtm_ctx* c, int64_t traj_begin, int64_t count, uint64_t seed) 
         int cols = c->o.tile_cols > 0 ? c->o.tile_cols : (c->o.precision == QTM_PREC_FP32 ? 4 : 2);
         lr = qtm::launch_sparse(a, S0.dev, c->o.precision, cols, c->stream, &li);
     } else {
-        int bpc = 0, lds = 0;
-        if (qtm::dense_occupancy(S0.d, c->o.precision, c->o.tile_cols, &bpc, &lds)) bpc = 1;
-        lr = qtm::launch_dense(a, S0.dev, S0.d, c->o.precision, bpc, c->stream, &li);
+        if (qtm::wave_supported(S0.d)) {
+            // one wavefront per 16 trajectories; tile_cols selects waves per block (16..64 columns)
+            lr = qtm::launch_wave(a, S0.dev, c->o.precision, c->o.team_waves, c->stream, &li);
+        } else {
+            int bpc = 0, lds = 0;
+            if (qtm::dense_occupancy(S0.d, c->o.precision, c->o.tile_cols, &bpc, &lds)) bpc = 1;
+            lr = qtm::launch_dense(a, S0.dev, S0.d, c->o.precision, bpc, c->stream, &li);
+        }
     }
     if (lr) return fail(QTM_E_DEVICE, "kernel launch failed (%d): %s", lr, hipGetErrorString(hipGetLastError()));
     HIPCHECK(hipEventRecord(c->ev1, c->stream));

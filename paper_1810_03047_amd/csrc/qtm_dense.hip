@@ -43,6 +43,7 @@ __global__ void __launch_bounds__(512) traj_dense_kernel(RunArgs a, int lds_m) {
     __syncthreads();
     Body<DenseLayout<T, PREC>> B(L, S, a, cs, flags);
     B.run();
+    if (threadIdx.x == 0) atomicAdd(&a.counters[0], B.passes);
 }
 
 // Trajectory average in index order: one thread per (observable, time).

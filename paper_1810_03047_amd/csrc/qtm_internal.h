@@ -31,6 +31,8 @@ struct DevSystem {
     // right-hand-side operator M = -i H_eff
     const double* Mfrag;       // dense: (2dp)^2 doubles in MFMA A-fragment order
     const float* Mfrag32;      // same, rounded to FP32
+    const double* Mc64;        // dense, d <= 64: complex-compressed fragments for the team kernel
+    const float* Mc32;         // same layout for FP32 products
     const int* sl_off;         // sparse: sliced ELL, 64-row slices; entry offset of each slice
     const int* sl_w;           // width of each slice
     const int* sl_col;         // [slice entries], column-major inside a slice
@@ -79,7 +81,7 @@ struct RunArgs {
 };
 
 // Host-side launchers (defined in qtm_kernels.hip).
-struct LaunchInfo { int blocks, threads, lds, cols; };
+struct LaunchInfo { int blocks, threads, lds, cols, shape; };
 int launch_dense(const RunArgs& a, const DevSystem& s0, int max_d, int prec, int blocks_per_cu,
                  hipStream_t st, LaunchInfo* info);
 int launch_sparse(const RunArgs& a, const DevSystem& s0, int prec, int cols, hipStream_t st, LaunchInfo* info);
@@ -90,5 +92,9 @@ int launch_mlp_grad(const float* P, const float* feat, const float* tgt, const i
                     float* partial, float* loss_part, float* grad, float* loss, hipStream_t st);
 int launch_mlp_adam(float* master, float* work, const float* grad, float* m, float* v, float lr, int step, hipStream_t st);
 int mlp_partial_rows(int n);
+// wave-per-tile dense kernel (qtm_wave.hip), d <= 64
+int wave_supported(int d);
+int launch_wave(const RunArgs& a, const DevSystem& s0, int prec, int waves_per_team, hipStream_t st, LaunchInfo* info);
+int team_candidates(int d, int* waves, int cap);
 
 }  // namespace qtm

@@ -23,6 +23,7 @@ __global__ void __launch_bounds__(1024) traj_sparse_kernel(RunArgs a) {
     L.red = (double*)p;
     Body<SparseLayout<RPT, NBC, PREC>> B(L, S, a, cs, flags);
     B.run();
+    if (threadIdx.x == 0) atomicAdd(&a.counters[0], B.passes);
 }
 
 int launch_sparse(const RunArgs& a, const DevSystem& s0, int prec, int cols, hipStream_t st, LaunchInfo* info) {

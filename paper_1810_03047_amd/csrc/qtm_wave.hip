@@ -1,0 +1,849 @@
+// qtm_wave.hip -- trajectory kernel for small dense H_eff (d <= 64): a "team"
+// of NWT wavefronts owns 16 trajectories (lane & 15); the team's waves split
+// the row tiles of the real-embedded operator (T tiles each), so every lane
+// holds 2*T complex state components of its trajectory and the whole DOPRI5
+// state stays in registers.  A block holds one team, or up to four single-wave
+// teams that share the operator in LDS.
+//
+// The product K = M W runs on the matrix cores (16x16x4 MFMA, FP64 or FP32):
+// W is staged in the team's LDS tile and M's A-fragments (real embedding) are
+// read from LDS, one value per lane and MFMA, prefetched one k-block ahead.
+//
+// Per-trajectory scalars (t, h, threshold, ...) are replicated on the four lane
+// groups and on the team's waves, which all take identical decisions from
+// identical reductions: within a wave two xor-shuffles, across the team one LDS
+// exchange summed in wave order.  Only the team's own waves meet at barriers,
+// and every barrier sits in control flow that is uniform across the team.
+#include "qtm_body.h"
+
+namespace qtm {
+
+__device__ __forceinline__ double csum(double x) {
+    x += __shfl_xor(x, 16);
+    x += __shfl_xor(x, 32);
+    return x;
+}
+__device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ULL; }
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+constexpr int kXV = 8;       // values per column in one team reduction
+
+template <int T, int NWT, int PREC>
+struct Team {
+    typedef typename MfmaT<PREC>::in_t in_t;
+    typedef typename std::conditional<PREC == 0, double2, float2>::type kv_t;   // stage vectors
+    static constexpr int NE = 2 * T;
+
+    const DevSystem& S;
+    const RunArgs& A;
+    const in_t* Mf;          // LDS: A-fragments of the real-embedded operator [RT][KB][64]
+    in_t* Wb;                // LDS: operand tile [2dp][16]
+    double2* St;             // alias of Wb: complex staging [dp][16]
+    double* Xb;              // LDS: team reduction exchange [NWT][16][kXV]
+    unsigned long long* Ib;  // LDS: trajectory hand-out [16]
+    int* Fb;                 // LDS: team flags [4]
+    const double2* Od;       // LDS copy of the diagonal observables [n_e][d] (when od_lds)
+    int od_lds;
+    int lane, lg, c16, wv, RT, KB, d, dp;
+
+    // per-lane trajectory state (identical on every lane of a column, on every wave)
+    double t, h, h0, d1, r, u, tseg, tb, fac, th, oth, tnext;
+    long long traj;
+    int state, action, seg, kk, nacc, nrej, njump, natt, last, rejected, omode, ch, seg_rec, first_acc;
+    bool exhausted;
+    unsigned long long passes;
+
+    double2 y[NE], yn[NE];
+    kv_t k[7][NE];
+    double2 es[NE], ds[NE];  // sum_j e_j k_j and sum_j d_j k_j over stages 1..6
+
+    QTM_DI Team(const DevSystem& s, const RunArgs& a) : S(s), A(a) {}
+
+    QTM_DI void team_sync() const {
+        if (NWT > 1) __syncthreads();
+        else wave_sync();
+    }
+    QTM_DI int qraw(int e) const {
+        int rt = wv * T + (e >> 1);
+        return rt < RT ? RowMap<PREC>::comp(rt, lg, e & 1) : -1;
+    }
+    QTM_DI int comp(int e) const { int q = qraw(e); return q < d ? q : -1; }
+
+    // team-wide per-column sums of NV values (NV <= kXV), identical on every lane
+    template <int NV> QTM_DI void tsum(double (&p)[NV]) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) p[v] = csum(p[v]);
+        if (NWT == 1) return;
+        if (lg == 0) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) Xb[(wv * 16 + c16) * kXV + v] = p[v];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            double s = 0.0;
+#pragma unroll
+            for (int g = 0; g < NWT; ++g) s += Xb[(g * 16 + c16) * kXV + v];
+            p[v] = s;
+        }
+        __syncthreads();
+    }
+    QTM_DI double tsum1(double x) { double p[1] = {x}; tsum<1>(p); return p[0]; }
+    QTM_DI bool team_any(bool pred) {
+        bool w = wave_any(pred);
+        if (NWT == 1) return w;
+        if (lane == 0) Fb[wv] = w ? 1 : 0;
+        __syncthreads();
+        bool any = false;
+#pragma unroll
+        for (int g = 0; g < NWT; ++g) any |= Fb[g] != 0;
+        __syncthreads();
+        return any;
+    }
+
+    // ------------------------------------------------------------ product
+    QTM_DI void put(int e, double2 v) {
+        int q = qraw(e);
+        if (q < 0) return;
+        Wb[RowMap<PREC>::row(q, 0) * 16 + c16] = q < d ? (in_t)v.x : (in_t)0;
+        Wb[RowMap<PREC>::row(q, 1) * 16 + c16] = q < d ? (in_t)v.y : (in_t)0;
+    }
+    // K = M W for the team's 16 columns (W staged by put()).  A-fragments of the
+    // real-embedded operator are read from LDS (one value per lane and MFMA) and
+    // prefetched one k-block ahead; padded tiles (rt >= RT) read a valid tile and
+    // their results are never used, so the loop has no branches.
+    QTM_DI void product(kv_t (&K)[NE]) {
+        team_sync();
+        typename MfmaT<PREC>::acc_t acc[T];
+        const in_t* ap[T];
+#pragma unroll
+        for (int tt = 0; tt < T; ++tt) {
+            acc[tt] = 0;
+            int rt = wv * T + tt;
+            rt = rt < RT ? rt : RT - 1;
+            ap[tt] = Mf + (size_t)rt * KB * 64 + lane;
+        }
+        const in_t* bb = Wb + lg * 16 + c16;
+        in_t bn = bb[0];
+        in_t an[T];
+#pragma unroll
+        for (int tt = 0; tt < T; ++tt) an[tt] = ap[tt][0];
+        for (int kb = 0; kb < KB; ++kb) {
+            const in_t bc = bn;
+            in_t ac[T];
+#pragma unroll
+            for (int tt = 0; tt < T; ++tt) ac[tt] = an[tt];
+            const int kn = kb + 1 < KB ? kb + 1 : kb;
+            bn = bb[(4 * kn) * 16];
+#pragma unroll
+            for (int tt = 0; tt < T; ++tt) an[tt] = ap[tt][(size_t)kn * 64];
+#pragma unroll
+            for (int tt = 0; tt < T; ++tt) acc[tt] = MfmaT<PREC>::op(ac[tt], bc, acc[tt]);
+        }
+#pragma unroll
+        for (int tt = 0; tt < T; ++tt) {
+            K[2 * tt + 0] = from_d2<kv_t>(make_double2((double)acc[tt][0], (double)acc[tt][1]));
+            K[2 * tt + 1] = from_d2<kv_t>(make_double2((double)acc[tt][2], (double)acc[tt][3]));
+        }
+        team_sync();
+        ++passes;       // summed into the run counters once, when the team exits
+    }
+
+    // ------------------------------------------------------------ dense output
+    // u(th) = y + th (D + (1-th)(B + th (R4 + (1-th) R5))),
+    // D = yn - y, B = h k1 - D, R4 = D - h k7 - B, R5 = h sum_j d_j k_j
+    QTM_DI double2 dense_at(int e, double tht) const {
+        double2 D = csub(yn[e], y[e]);
+        double2 B = csub(cscale(h, to_d2(k[0][e])), D);
+        double2 R4 = csub(csub(D, cscale(h, to_d2(k[6][e]))), B);
+        double2 R5 = cscale(h, cfma(dp_d(6), to_d2(k[6][e]), ds[e]));
+        double t1 = 1.0 - tht;
+        double2 in = cadd(R4, cscale(t1, R5));
+        in = cadd(B, cscale(tht, in));
+        in = cadd(D, cscale(t1, in));
+        return cadd(y[e], cscale(tht, in));
+    }
+    QTM_DI double2 vec_mode(int e) const { return omode == 1 ? y[e] : omode == 2 ? yn[e] : dense_at(e, oth); }
+
+    QTM_DI double2 csr_row(const int* rp, const int* ci, const double2* val, int q) const {
+        double2 s = make_double2(0.0, 0.0);
+        for (int p = rp[q]; p < rp[q + 1]; ++p) s = cadd(s, cmul(val[p], St[ci[p] * 16 + c16]));
+        return s;
+    }
+    QTM_DI void stage_vec(const double2 (&v)[NE]) {
+        team_sync();   // earlier readers of the staging tile are done
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+            int q = comp(e);
+            if (q >= 0) St[q * 16 + c16] = v[e];
+        }
+        team_sync();
+    }
+
+    // ------------------------------------------------------------ outputs
+    // <u|O_o|u>/<u|u> for every lane with omode != 0 (one team reduction per observable)
+    QTM_DI void output_round(bool on) {
+        double2 uu[NE];
+        double nn = 0.0;
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+            int q = comp(e);
+            uu[e] = (on && q >= 0) ? vec_mode(e) : make_double2(0.0, 0.0);
+            nn += cabs2(uu[e]);
+        }
+        nn = tsum1(nn);
+        if (S.any_csr_e) stage_vec(uu);
+        for (int o = 0; o < S.n_e; ++o) {
+            double p[2] = {0.0, 0.0};
+            const bool diag = S.e_fmt[o] == 2;
+            const double2* dv = od_lds ? Od + (size_t)o * d : S.e_val + S.e_doff[o];
+            const int* rp = S.e_rp + (size_t)o * (S.d + 1);
+#pragma unroll
+            for (int e = 0; e < NE; ++e) {
+                int q = comp(e);
+                if (q < 0 || !on) continue;
+                if (diag) {
+                    double a2 = cabs2(uu[e]);
+                    double2 v = dv[q];
+                    p[0] += v.x * a2;
+                    p[1] += v.y * a2;
+                } else {
+                    double2 Ou = csr_row(rp, S.e_ci, S.e_val, q);
+                    p[0] += uu[e].x * Ou.x + uu[e].y * Ou.y;     // Re conj(u) O u
+                    p[1] += uu[e].x * Ou.y - uu[e].y * Ou.x;     // Im conj(u) O u
+                }
+            }
+            tsum<2>(p);
+            if (on && lg == 0 && wv == 0) S.X[((size_t)traj * S.n_e + o) * S.n_t + kk] = make_double2(p[0] / nn, p[1] / nn);
+        }
+    }
+
+    // phase 0: new trajectory (t_k == t); 1: accepted step (t < t_k <= tb) or jump
+    // step (t < t_k < tb); 3: after a jump (t_k == t, current y)
+    QTM_DI void next_output(int phase) {
+        omode = 0;
+        if (kk >= S.n_t) return;
+        const double tk = tnext;
+        if (phase == 0 && state == ST_NEW) {
+            if (tk == t) omode = 1;
+        } else if (phase == 1 && action == ACT_ACCEPT) {
+            if (tk <= tb) {
+                if (tk == tb) omode = 2;
+                else { omode = 3; oth = (tk - t) / h; }
+            }
+        } else if (phase == 1 && action == ACT_JUMP) {
+            if (tk < tb) { omode = 3; oth = (tk - t) / h; }
+        } else if (phase == 3 && action == ACT_POSTJUMP) {
+            if (tk == t) omode = 1;
+        }
+    }
+    QTM_DI void outputs_loop(int phase) {
+        for (;;) {
+            next_output(phase);
+            bool on = omode != 0;
+            if (!team_any(on)) break;
+            output_round(on);
+            if (on) {
+                kk++;
+                tnext = kk < S.n_t ? S.tlist[kk] : 0.0;
+            }
+        }
+        omode = 0;
+    }
+
+    QTM_DI void retire(bool failed) {
+        if (lg == 0 && wv == 0) {
+            int* st = S.tstat + (size_t)traj * 4;
+            st[0] = nacc; st[1] = nrej; st[2] = seg + 1; st[3] = njump;
+            S.jn[traj] = njump;
+            if (failed) atomicMin((unsigned long long*)A.fail, (unsigned long long)(S.traj_begin + traj));
+        }
+        state = ST_EMPTY;
+        traj = -1;
+    }
+
+    // ------------------------------------------------------------ main loop
+    QTM_DI void run() {
+        const double tend = S.tend;
+        state = ST_EMPTY; traj = -1; action = ACT_NONE; omode = 0; exhausted = false;
+        t = h = h0 = d1 = r = u = tseg = tb = fac = th = oth = tnext = 0.0;
+        seg = kk = nacc = nrej = njump = natt = last = rejected = ch = seg_rec = first_acc = 0;
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+            y[e] = yn[e] = es[e] = ds[e] = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int j = 0; j < 7; ++j) k[j][e] = from_d2<kv_t>(make_double2(0.0, 0.0));
+        }
+        long long cycles = 0;
+        bool first = true;
+        passes = 0;
+        for (;;) {
+            // ---- refill empty slots (wave 0 takes the indices, the team reads them)
+            action = ACT_NONE;
+            bool want = state == ST_EMPTY && !exhausted && (A.persistent || first);
+            first = false;
+            if (wv == 0 && lg == 0) Ib[c16] = want ? atomicAdd(S.queue, 1ULL) : 0ULL;
+            team_sync();
+            unsigned long long idx = Ib[c16];
+            team_sync();
+            if (want) {
+                if ((long long)idx < S.count) {
+                    traj = (long long)idx;
+                    t = S.t0; seg = 0; kk = 0; nacc = nrej = njump = natt = 0;
+                    rejected = 0; seg_rec = 0;
+                    tnext = S.tlist[0];
+                    state = ST_NEW;
+                } else {
+                    exhausted = true;
+                }
+            }
+            if (!team_any(state != ST_EMPTY)) break;
+            if (++cycles > A.max_cycles) {      // failsafe: retire everything as failed
+                if (state != ST_EMPTY) retire(true);
+                break;
+            }
+            if (team_any(state == ST_NEW)) {
+#pragma unroll
+                for (int e = 0; e < NE; ++e) {
+                    int q = comp(e);
+                    if (state == ST_NEW) y[e] = q >= 0 ? S.psi0[q] : make_double2(0.0, 0.0);
+                }
+                outputs_loop(0);
+                if (state == ST_NEW) state = ST_NEEDK1;
+            }
+            // ---- segment start: threshold r and channel uniform (Philox)
+            if (state == ST_NEEDK1) {
+                if (!(t < tend)) retire(false);
+                else if (natt >= A.max_steps) retire(true);
+                else {
+                    uint64_t ctr[4] = {(uint64_t)(S.traj_begin + traj), (uint64_t)seg, 0, 0};
+                    philox4x64(ctr, A.seed, S.key1);
+                    r = u53(ctr[0]);
+                    u = u53(ctr[1]);
+                    first_acc = 1;
+                    tseg = t;
+                    rejected = 0;
+                }
+            }
+            if (team_any(state == ST_NEEDK1)) segment_start();
+            // the last step of the span ends exactly at t_end
+            if (state == ST_STEP) {
+                last = (t + h >= tend);
+                if (last) h = tend - t;
+            }
+            stages();
+            post_step();
+        }
+    }
+
+    // k1 = M y, then the starting step (or the learned proposal)
+    QTM_DI void segment_start() {
+        kv_t K[NE];
+#pragma unroll
+        for (int e = 0; e < NE; ++e) put(e, y[e]);
+        product(K);
+#pragma unroll
+        for (int e = 0; e < NE; ++e)
+            if (state == ST_NEEDK1) k[0][e] = K[e];
+        if (A.learned || A.seg_cap > 0) features();
+        if (!A.learned) {
+            // Hairer-Norsett-Wanner starting step, first part: d0 = ||y/sc||, d1 = ||f0/sc||
+            double p[2] = {0.0, 0.0};
+#pragma unroll
+            for (int e = 0; e < NE; ++e) {
+                int q = comp(e);
+                if (q < 0) continue;
+                double sc = A.atol + A.rtol * sqrt(cabs2(y[e]));
+                double isc2 = 1.0 / (sc * sc);
+                p[0] += cabs2(y[e]) * isc2;
+                p[1] += cabs2(to_d2(k[0][e])) * isc2;
+            }
+            tsum<2>(p);
+            if (state == ST_NEEDK1) {
+                double dd0 = sqrt(p[0] / S.d), dd1 = sqrt(p[1] / S.d);
+                double hh = (dd0 < 1e-5 || dd1 < 1e-5) ? 1e-6 : 0.01 * dd0 / dd1;
+                h0 = fmin(hh, S.tend - t);
+                d1 = dd1;
+                state = ST_NEEDF1;
+            }
+        }
+    }
+
+    // 16 segment-start features; the learned form turns them into the first step
+    QTM_DI void features() {
+        const bool on = state == ST_NEEDK1;
+        if (S.n_c > 0) {
+            double2 v[NE];
+#pragma unroll
+            for (int e = 0; e < NE; ++e) v[e] = on ? y[e] : make_double2(0.0, 0.0);
+            stage_vec(v);
+        }
+        float f[kNF];
+        double nn = 0.0;
+#pragma unroll
+        for (int e = 0; e < NE; ++e)
+            if (on && comp(e) >= 0) nn += cabs2(y[e]);
+        nn = tsum1(nn);
+        for (int fi = 0; fi < 12; ++fi) {
+            double acc = 0.0;
+            if (fi < S.n_f) {
+                const double* fd = S.f_diag + (size_t)fi * S.d;
+#pragma unroll
+                for (int e = 0; e < NE; ++e) {
+                    int q = comp(e);
+                    if (on && q >= 0) acc += fd[q] * cabs2(y[e]);
+                }
+                acc = tsum1(acc);
+            }
+            f[fi] = (float)(acc / nn);
+        }
+        for (int n = 0; n < 2; ++n) {
+            double acc = 0.0;
+            if (n < S.n_c) {
+                const int* rp = S.c_rp + (size_t)n * (S.d + 1);
+#pragma unroll
+                for (int e = 0; e < NE; ++e) {
+                    int q = comp(e);
+                    if (on && q >= 0) acc += cabs2(csr_row(rp, S.c_ci, S.c_val, q));
+                }
+                acc = tsum1(acc);
+            }
+            f[12 + n] = (float)(acc / nn);
+        }
+        if (on) {
+            f[14] = logf((float)r);
+            f[15] = (float)((t - S.t0) / (S.tend - S.t0));
+            if (A.learned) {
+                float lh = mlp_logh(A.mlp, f);
+                // snap to the grid 2^(k/4), k = round(4 log2 h)
+                double hh = exp2_quarter((int)rint(4.0 * ((double)lh / 0.69314718055994530942)));
+                h = fmin(hh, S.tend - t);
+                state = ST_STEP;
+            }
+            if (A.seg_cap > 0 && seg_rec < A.seg_cap && lg == 0 && wv == 0) {
+                float* rec = S.segs + ((size_t)traj * A.seg_cap + seg_rec) * kSegRec;
+#pragma unroll
+                for (int v = 0; v < kNF; ++v) rec[v] = f[v];
+                rec[16] = 0.f; rec[17] = -1.f; rec[18] = 1.f; rec[19] = 1.f;
+            }
+        }
+    }
+
+    // stage s (0-based): w = y + sum_j c_j k_j, k_s = M w
+    template <int s> QTM_DI void one_stage() {
+        double cf[6];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) cf[j] = (state == ST_STEP) ? h * dp_a(s, j) : 0.0;
+        if (s == 1 && state == ST_NEEDF1) cf[0] = h0;
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+            double2 acc;
+            if constexpr (PREC == 0) {
+                acc = y[e];
+#pragma unroll
+                for (int j = 0; j < s; ++j)
+                    if (dp_a(s, j) != 0.0 || (s == 1 && j == 0)) acc = cfma(cf[j], to_d2(k[j][e]), acc);
+            } else {
+                // FP32 form: the increment sum_j c_j k_j of FP32 products is formed in FP32
+                // and added to the FP64 state
+                float2 inc = make_float2(0.f, 0.f);
+#pragma unroll
+                for (int j = 0; j < s; ++j)
+                    if (dp_a(s, j) != 0.0 || (s == 1 && j == 0)) {
+                        float2 kj = (float2&)k[j][e];
+                        inc.x = fmaf((float)cf[j], kj.x, inc.x);
+                        inc.y = fmaf((float)cf[j], kj.y, inc.y);
+                    }
+                acc = make_double2(y[e].x + (double)inc.x, y[e].y + (double)inc.y);
+            }
+            put(e, acc);
+            if (s == 6) {
+                // y_new is the last stage input; fold k1..k6 into the error and
+                // dense-output sums now so that k2..k6 need not live longer
+                yn[e] = acc;
+                double2 se = make_double2(0.0, 0.0), sd = make_double2(0.0, 0.0);
+#pragma unroll
+                for (int j = 0; j < 6; ++j) {
+                    if (dp_e(j) != 0.0) se = cfma(dp_e(j), to_d2(k[j][e]), se);
+                    if (dp_d(j) != 0.0) sd = cfma(dp_d(j), to_d2(k[j][e]), sd);
+                }
+                es[e] = se;
+                ds[e] = sd;
+            }
+        }
+        product(k[s]);
+    }
+
+    QTM_DI void stages() {
+        one_stage<1>();
+        if (team_any(state == ST_NEEDF1)) {
+            // starting step, second part: d2 = ||(f1 - f0)/sc|| / h0
+            double p0 = 0.0;
+#pragma unroll
+            for (int e = 0; e < NE; ++e) {
+                int q = comp(e);
+                if (q < 0) continue;
+                double sc = A.atol + A.rtol * sqrt(cabs2(y[e]));
+                p0 += cabs2(csub(to_d2(k[1][e]), to_d2(k[0][e]))) / (sc * sc);
+            }
+            p0 = tsum1(p0);
+            if (state == ST_NEEDF1) {
+                double d2 = sqrt(p0 / S.d) / h0;
+                double h1 = (d1 <= 1e-15 && d2 <= 1e-15) ? fmax(1e-6, h0 * 1e-3) : 1.0 / inv_fifth_root(0.01 / fmax(d1, d2));
+                h = fmin(fmin(100.0 * h0, h1), S.tend - t);
+                state = ST_PROBED;
+            }
+        }
+        one_stage<2>();
+        one_stage<3>();
+        one_stage<4>();
+        one_stage<5>();
+        one_stage<6>();
+    }
+
+    QTM_DI void post_step() {
+        const double tend = S.tend;
+        double p[2] = {0.0, 0.0};
+        if (state == ST_STEP) {
+#pragma unroll
+            for (int e = 0; e < NE; ++e) {
+                int q = comp(e);
+                if (q < 0) continue;
+                double2 er = cscale(h, cfma(dp_e(6), to_d2(k[6][e]), es[e]));
+                double sc = A.atol + A.rtol * fmax(sqrt(cabs2(y[e])), sqrt(cabs2(yn[e])));
+                p[0] += cabs2(er) / (sc * sc);
+                p[1] += cabs2(yn[e]);
+            }
+        }
+        tsum<2>(p);
+        action = ACT_NONE;
+        if (state == ST_PROBED) state = ST_STEP;
+        else if (state == ST_STEP) {
+            natt++;
+            double err = sqrt(p[0] / S.d);
+            if (!(err <= 1.0)) {
+                double f = isfinite(err) ? fmax(0.2, 0.9 * inv_fifth_root(err)) : 0.2;
+                h *= f;
+                rejected = 1;
+                nrej++;
+                action = ACT_REJECT;
+                if (!(h > 16.0 * DBL_EPSILON * fabs(t)) || natt >= A.max_steps) action = ACT_FAIL;
+            } else {
+                nacc++;
+                double fc = (err == 0.0) ? 10.0 : fmin(10.0, 0.9 * inv_fifth_root(err));
+                if (rejected) fc = fmin(1.0, fc);
+                fac = fc;
+                if (A.seg_cap > 0 && first_acc && seg_rec < A.seg_cap && lg == 0 && wv == 0)
+                    S.segs[((size_t)traj * A.seg_cap + seg_rec) * kSegRec + 17] = (float)(h * fc);
+                first_acc = 0;
+                tb = last ? tend : t + h;
+                if (S.n_c > 0 && p[1] < r) action = ACT_JUMP;
+                else {
+                    action = ACT_ACCEPT;
+                    if (!last && natt >= A.max_steps) action = ACT_FAIL;
+                }
+            }
+        }
+        const bool anyj = team_any(action == ACT_JUMP);
+        if (anyj) jump_time();
+        if (team_any(action == ACT_ACCEPT || action == ACT_JUMP)) outputs_loop(1);
+        if (anyj) do_jump();
+        if (action == ACT_ACCEPT) {
+#pragma unroll
+            for (int e = 0; e < NE; ++e) { y[e] = yn[e]; k[0][e] = k[6][e]; }
+            t = tb;
+            h *= fac;
+            rejected = 0;
+            if (!(t < tend)) retire(false);
+        } else if (action == ACT_FAIL) {
+            retire(true);
+        }
+    }
+
+    // Jump time: first theta in [0,1] with ||u(theta)||^2 = r, from the Gram matrix of
+    // v = {y, D, B, R4, R5}: u = sum_p c_p v_p, c = (1, th, th(1-th), th^2(1-th), th^2(1-th)^2)
+    QTM_DI void jump_time() {
+        const bool on = action == ACT_JUMP;
+        double g0[8], g1[7];
+#pragma unroll
+        for (int n = 0; n < 8; ++n) g0[n] = 0.0;
+#pragma unroll
+        for (int n = 0; n < 7; ++n) g1[n] = 0.0;
+        if (on) {
+#pragma unroll
+            for (int e = 0; e < NE; ++e) {
+                int q = comp(e);
+                if (q < 0) continue;
+                double2 v[5];
+                v[0] = y[e];
+                v[1] = csub(yn[e], y[e]);
+                v[2] = csub(cscale(h, to_d2(k[0][e])), v[1]);
+                v[3] = csub(csub(v[1], cscale(h, to_d2(k[6][e]))), v[2]);
+                v[4] = cscale(h, cfma(dp_d(6), to_d2(k[6][e]), ds[e]));
+                int n = 0;
+#pragma unroll
+                for (int a = 0; a < 5; ++a)
+#pragma unroll
+                    for (int b = a; b < 5; ++b) {
+                        double gv = v[a].x * v[b].x + v[a].y * v[b].y;
+                        if (n < 8) g0[n] += gv; else g1[n - 8] += gv;
+                        ++n;
+                    }
+            }
+        }
+        tsum<8>(g0);
+        tsum<7>(g1);
+        if (on) {
+            auto f = [&](double x) {
+                double t1 = 1.0 - x;
+                double cc[5] = {1.0, x, x * t1, x * x * t1, x * x * t1 * t1};
+                double s = 0.0;
+                int n = 0;
+#pragma unroll
+                for (int a = 0; a < 5; ++a)
+#pragma unroll
+                    for (int b = a; b < 5; ++b) {
+                        double g = n < 8 ? g0[n] : g1[n - 8];
+                        s += (a == b ? 1.0 : 2.0) * cc[a] * cc[b] * g;
+                        ++n;
+                    }
+                return s - r;
+            };
+            double lo = 0.0, hi = 1.0;
+            for (int m = 1; m <= 32; ++m) {
+                double x = (double)m / 32.0;
+                if (f(x) < 0.0) { hi = x; lo = (double)(m - 1) / 32.0; break; }
+            }
+            while (hi - lo > 1e-13) {
+                double mid = 0.5 * (lo + hi);
+                if (f(mid) < 0.0) hi = mid; else lo = mid;
+            }
+            th = 0.5 * (lo + hi);
+            tb = t + th * h;
+        }
+    }
+
+    // ||C_n psi*||^2 for this lane's trajectory (psi* staged); uniform call
+    QTM_DI double chan_prob(int n, bool on) {
+        const int* rp = S.c_rp + (size_t)n * (S.d + 1);
+        double acc = 0.0;
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+            int q = comp(e);
+            if (on && q >= 0) acc += cabs2(csr_row(rp, S.c_ci, S.c_val, q));
+        }
+        return tsum1(acc);
+    }
+
+    QTM_DI void do_jump() {
+        const bool on = action == ACT_JUMP;
+        {
+            double2 ps[NE];
+#pragma unroll
+            for (int e = 0; e < NE; ++e) ps[e] = (on && comp(e) >= 0) ? dense_at(e, th) : make_double2(0.0, 0.0);
+            stage_vec(ps);                      // psi* = u(theta*)
+        }
+        // channel: smallest n with sum_{m<=n} p_m >= u * sum p (two uniform passes)
+        double tot = 0.0;
+        for (int n = 0; n < S.n_c; ++n) tot += chan_prob(n, on);
+        const double thr = u * tot;
+        double cum = 0.0, plast = 0.0, pch = 0.0;
+        int lastpos = -1, chosen = -1;
+        for (int n = 0; n < S.n_c; ++n) {
+            double pv = chan_prob(n, on);
+            cum += pv;
+            if (pv > 0.0) { lastpos = n; plast = pv; }
+            if (chosen < 0 && pv > 0.0 && cum >= thr) { chosen = n; pch = pv; }
+        }
+        if (tot > 0.0 && chosen < 0) { chosen = lastpos; pch = plast; }   // rounding left none: last with p > 0
+        if (!(tot > 0.0)) chosen = -1;
+        if (on) ch = chosen;
+        // y <- C_ch psi* / sqrt(p_ch)  (no channel: renormalised psi*)
+        double nrm = 0.0;
+        if (on) {
+#pragma unroll
+            for (int e = 0; e < NE; ++e) {
+                int q = comp(e);
+                if (q < 0) { y[e] = make_double2(0.0, 0.0); continue; }
+                if (ch >= 0) y[e] = cscale(1.0 / sqrt(pch), csr_row(S.c_rp + (size_t)ch * (S.d + 1), S.c_ci, S.c_val, q));
+                else { y[e] = St[q * 16 + c16]; nrm += cabs2(y[e]); }
+            }
+        }
+        nrm = tsum1(nrm);
+        if (on && ch < 0) {
+#pragma unroll
+            for (int e = 0; e < NE; ++e) y[e] = cscale(1.0 / sqrt(nrm), y[e]);
+        }
+        if (on) {
+            if (lg == 0 && wv == 0) {
+                if (njump < A.jcap) {
+                    S.jt[(size_t)traj * A.jcap + njump] = tb;
+                    S.jc[(size_t)traj * A.jcap + njump] = ch;
+                }
+                if (A.seg_cap > 0 && seg_rec < A.seg_cap) {
+                    float* rec = S.segs + ((size_t)traj * A.seg_cap + seg_rec) * kSegRec;
+                    rec[16] = (float)(tb - tseg);
+                    rec[18] = 0.f;
+                }
+            }
+            njump++;
+            t = tb;
+            action = ACT_POSTJUMP;
+        }
+        outputs_loop(3);
+        if (action == ACT_POSTJUMP) {
+            action = ACT_NONE;
+            seg++;
+            seg_rec++;
+            state = ST_NEEDK1;
+        }
+    }
+};
+
+// LDS of a block: [A-fragments of M][per team: operand tile, team exchange, hand-out, flags]
+// [diagonal observables].  Blocks of single-wave teams hold TPB teams that share M
+// and never meet at a barrier after the set-up.
+struct TeamLds { size_t m, team, w, x, ib, fb, od, total; };
+static __host__ __device__ TeamLds team_lds(int dp, int d, int n_e, int prec, int nwt, int tpb, int od_lds) {
+    TeamLds L;
+    size_t es = prec == 0 ? 8 : 4;
+    L.m = 0;
+    L.w = (((size_t)(2 * dp) * (2 * dp) * es) + 15) & ~(size_t)15;       // first team's tile
+    L.x = (size_t)2 * dp * 16 * sizeof(double);                             // offsets inside a team
+    L.ib = L.x + (size_t)nwt * 16 * kXV * sizeof(double);
+    L.fb = L.ib + 16 * sizeof(unsigned long long);
+    L.team = (L.fb + 16 + 15) & ~(size_t)15;                                // bytes per team
+    L.od = L.w + (size_t)tpb * L.team;
+    L.total = L.od + (od_lds ? (size_t)n_e * d * sizeof(double2) : 0);
+    return L;
+}
+
+template <int T, int NWT, int PREC>
+__global__ void __launch_bounds__(NWT == 1 ? 256 : 64 * NWT) traj_team_kernel(RunArgs a, int od_lds, int tpb) {
+    typedef typename MfmaT<PREC>::in_t in_t;
+    extern __shared__ double smem[];
+    const DevSystem& S = a.sys[0];
+    const TeamLds L = team_lds(S.dp, S.d, S.n_e, PREC, NWT, tpb, od_lds);
+    char* base = (char*)smem;
+    const in_t* Mg = MfmaT<PREC>::frag(S);
+    in_t* Ml = (in_t*)(base + L.m);
+    const size_t nm = (size_t)(2 * S.dp) * (2 * S.dp);
+    for (size_t i = threadIdx.x; i < nm; i += blockDim.x) Ml[i] = Mg[i];
+    double2* Odl = (double2*)(base + L.od);
+    if (od_lds)
+        for (int o = 0; o < S.n_e; ++o)
+            for (int i = threadIdx.x; i < S.d; i += blockDim.x) Odl[(size_t)o * S.d + i] = S.e_val[S.e_doff[o] + i];
+    __syncthreads();
+    const int team = (threadIdx.x >> 6) / NWT;
+    char* tb = base + L.w + (size_t)team * L.team;
+    Team<T, NWT, PREC> W(S, a);
+    W.Mf = Ml;
+    W.Wb = (in_t*)tb;
+    W.St = (double2*)tb;
+    W.Xb = (double*)(tb + L.x);
+    W.Ib = (unsigned long long*)(tb + L.ib);
+    W.Fb = (int*)(tb + L.fb);
+    W.Od = Odl;
+    W.od_lds = od_lds;
+    W.lane = threadIdx.x & 63;
+    W.wv = (threadIdx.x >> 6) % NWT;
+    W.lg = W.lane >> 4;
+    W.c16 = W.lane & 15;
+    W.d = S.d;
+    W.dp = S.dp;
+    W.RT = 2 * S.dp / 16;
+    W.KB = 2 * S.dp / 4;
+    W.run();
+    if ((threadIdx.x & 63) == 0 && W.wv == 0) atomicAdd(&a.counters[0], W.passes);
+}
+
+#ifndef QTM_WAVE_INSTANCES
+// Instances live in per-shape translation units (qtm_wave_t*.hip) so that they
+// compile in parallel; each defines QTM_WAVE_INSTANCES.
+template <int T, int NWT, int PREC> const void* team_fn_inst();
+
+// Team shapes (T row tiles per wave, NWT waves per team) compiled for each number
+// of 16-row tiles RT = 2 dp / 16; the first entry of a row is the default.
+static const int kShapes[9][3][2] = {
+    {{0, 0}, {0, 0}, {0, 0}},
+    {{1, 1}, {0, 0}, {0, 0}},
+    {{1, 2}, {2, 1}, {0, 0}},
+    {{1, 3}, {2, 2}, {0, 0}},
+    {{1, 4}, {2, 2}, {0, 0}},
+    {{1, 5}, {3, 2}, {5, 1}},
+    {{1, 6}, {2, 3}, {3, 2}},
+    {{1, 7}, {4, 2}, {0, 0}},
+    {{1, 8}, {2, 4}, {4, 2}},
+};
+
+// waves_per_team: 0 = default shape, else the listed shape with that many waves
+static int team_shape(int rt, int waves_per_team, int* T, int* nwt) {
+    if (rt < 1 || rt > 8) return -1;
+    for (int i = 0; i < 3; ++i) {
+        int tt = kShapes[rt][i][0], nn = kShapes[rt][i][1];
+        if (!tt) break;
+        if (waves_per_team == 0 || waves_per_team == nn) { *T = tt; *nwt = nn; return 0; }
+    }
+    return -1;
+}
+
+static const void* team_fn(int T, int nwt, int prec) {
+#define QTM_TEAM_CASE(TT, NN) \
+    if (T == TT && nwt == NN) return prec == 0 ? team_fn_inst<TT, NN, 0>() : team_fn_inst<TT, NN, 1>();
+    QTM_TEAM_CASE(1, 1) QTM_TEAM_CASE(2, 1) QTM_TEAM_CASE(1, 2) QTM_TEAM_CASE(1, 3) QTM_TEAM_CASE(1, 4)
+    QTM_TEAM_CASE(2, 2) QTM_TEAM_CASE(1, 5) QTM_TEAM_CASE(3, 2) QTM_TEAM_CASE(5, 1) QTM_TEAM_CASE(1, 6)
+    QTM_TEAM_CASE(2, 3) QTM_TEAM_CASE(1, 7) QTM_TEAM_CASE(4, 2) QTM_TEAM_CASE(1, 8) QTM_TEAM_CASE(2, 4)
+#undef QTM_TEAM_CASE
+    return nullptr;
+}
+
+// Team sizes available for dimension d (waves per team), for the autotuner.
+int team_candidates(int d, int* waves, int cap) {
+    int dp = (d + 7) / 8 * 8, rt = 2 * dp / 16, n = 0;
+    if (rt < 1 || rt > 8) return 0;
+    for (int i = 0; i < 3 && n < cap; ++i)
+        if (kShapes[rt][i][0]) waves[n++] = kShapes[rt][i][1];
+    return n;
+}
+
+int wave_supported(int d) {
+    int dp = (d + 7) / 8 * 8, rt = 2 * dp / 16, T, nwt;
+    return team_shape(rt, 0, &T, &nwt) == 0;
+}
+
+int launch_wave(const RunArgs& a, const DevSystem& s0, int prec, int waves_per_team, hipStream_t st, LaunchInfo* info) {
+    int dp = s0.dp, rt = 2 * dp / 16, T, nwt;
+    if (team_shape(rt, waves_per_team, &T, &nwt)) return -1;
+    const void* fn = team_fn(T, nwt, prec);
+    if (!fn) return -1;
+    // diagonal observables are copied to LDS when every observable is diagonal
+    int od_lds = 1;
+    for (int o = 0; o < s0.n_e; ++o) if (s0.e_fmt[o] != 2) od_lds = 0;
+    // single-wave teams: up to 4 per block, sharing the operator in LDS
+    int tpb = nwt == 1 ? 4 : 1;
+    TeamLds L = team_lds(dp, s0.d, s0.n_e, prec, nwt, tpb, od_lds);
+    while (tpb > 1 && L.total > 160 * 1024) L = team_lds(dp, s0.d, s0.n_e, prec, nwt, --tpb, od_lds);
+    if (L.total > 160 * 1024) return -1;
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.total) != hipSuccess) return -3;
+    int dev = 0, ncu = 0, nb = 1;
+    const int threads = nwt * tpb * 64;
+    if (hipGetDevice(&dev) != hipSuccess) return -3;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return -3;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, threads, L.total) != hipSuccess || nb < 1) nb = 1;
+    const int cols = 16 * tpb;
+    long long need = (s0.count + cols - 1) / cols;
+    long long blocks = a.persistent ? (long long)ncu * nb : need;
+    if (blocks > need) blocks = need;
+    if (blocks < 1) blocks = 1;
+    void* args[] = {(void*)&a, (void*)&od_lds, (void*)&tpb};
+    if (hipLaunchKernel(fn, dim3((unsigned)blocks), dim3(threads), args, L.total, st) != hipSuccess) return -3;
+    if (info) { info->blocks = (int)blocks; info->threads = threads; info->lds = (int)L.total; info->cols = cols; info->shape = T * 100 + nwt; }
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+#endif  // QTM_WAVE_INSTANCES
+
+}  // namespace qtm
