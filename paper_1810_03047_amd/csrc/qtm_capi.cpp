@@ -168,33 +168,6 @@ std::vector<T> build_frag(const HCsr& M, int dp, int prec) {
     return f;
 }
 
-// Complex-compressed operator of the team kernel (see its product()):
-// FP64: entry [(rt * dp/4 + kp) * 32 + ql * 4 + jl] = M[8 rt + ql][4 kp + jl]
-// FP32: entry [(rt * dp/2 + kb) * 16 + ql * 2 + jl] = M[8 rt + ql][2 kb + jl]
-template <class T>
-std::vector<T> build_compressed(const HCsr& M, int dp, int prec) {
-    std::vector<cd> Md((size_t)dp * dp, 0.0);
-    for (int i = 0; i < M.d; ++i)
-        for (int p = M.rp[i]; p < M.rp[i + 1]; ++p) Md[(size_t)i * dp + M.ci[p]] += M.v[p];
-    const int RT = dp / 8;
-    std::vector<T> out((size_t)2 * dp * dp);
-    auto put = [&](size_t idx, cd z) { out[2 * idx] = (T)z.real(); out[2 * idx + 1] = (T)z.imag(); };
-    if (prec == 0) {
-        for (int rt = 0; rt < RT; ++rt)
-            for (int kp = 0; kp < dp / 4; ++kp)
-                for (int ql = 0; ql < 8; ++ql)
-                    for (int jl = 0; jl < 4; ++jl)
-                        put(((size_t)rt * (dp / 4) + kp) * 32 + ql * 4 + jl, Md[(size_t)(8 * rt + ql) * dp + 4 * kp + jl]);
-    } else {
-        for (int rt = 0; rt < RT; ++rt)
-            for (int kb = 0; kb < dp / 2; ++kb)
-                for (int ql = 0; ql < 8; ++ql)
-                    for (int jl = 0; jl < 2; ++jl)
-                        put(((size_t)rt * (dp / 2) + kb) * 16 + ql * 2 + jl, Md[(size_t)(8 * rt + ql) * dp + 2 * kb + jl]);
-    }
-    return out;
-}
-
 struct DevBuf {
     void* p = nullptr;
     size_t n = 0;
@@ -202,7 +175,8 @@ struct DevBuf {
 
 struct SysHost {
     int d = 0, n_c = 0, n_e = 0, n_t = 0, n_f = 0;
-    bool sparse = false;
+    bool sparse = false;       // sliced-ELL kernel (CSR H, or dense H with d > 128)
+    bool team = false;         // team kernel (dense, d <= 64); otherwise the block dense kernel
     qtm::DevSystem dev{};
     std::vector<double> tlist;
     std::vector<DevBuf> bufs;          // device allocations owned by the system
@@ -295,9 +269,12 @@ int setup_system(SysHost& S, const qtm_system& in, int idx, const qtm_opts& o, b
         if (!std::isfinite(in.tlist[k])) return fail(QTM_E_INVAL, "system %d: non-finite tlist", idx);
         if (k > 0 && !(in.tlist[k] > in.tlist[k - 1])) return fail(QTM_E_INVAL, "system %d: tlist not strictly increasing at %d", idx, k);
     }
-    S.sparse = allow_sparse && H->fmt == QTM_FMT_CSR;
-    if (!S.sparse && d > 128) return fail(QTM_E_INVAL, "system %d: dense kernels support d <= 128 (got %d); pass H in CSR", idx, d);
-    if (S.sparse && d > 2048) return fail(QTM_E_INVAL, "system %d: sparse kernel supports d <= 2048 (got %d)", idx, d);
+    // kernel choice: CSR H -> sliced-ELL SpMM; dense H -> MFMA team kernel (d <= 64),
+    // MFMA block kernel (d <= 128), or the SpMM kernel on full rows (d <= 2048)
+    (void)allow_sparse;
+    S.sparse = H->fmt == QTM_FMT_CSR || d > 128;
+    S.team = !S.sparse && qtm::wave_supported(d);
+    if (d > 2048) return fail(QTM_E_INVAL, "system %d: dimension %d above the supported 2048", idx, d);
     S.d = d; S.n_c = in.n_c; S.n_e = in.n_e; S.n_t = in.n_t;
     S.tlist.assign(in.tlist, in.tlist + in.n_t);
     qtm::DevSystem& D = S.dev;
@@ -312,8 +289,7 @@ int setup_system(SysHost& S, const qtm_system& in, int idx, const qtm_opts& o, b
         D.rt = 2 * dp / 16;
         if ((rc = upload(S, &D.Mfrag, build_frag<double>(M, dp, 0)))) return rc;
         if ((rc = upload(S, &D.Mfrag32, build_frag<float>(M, dp, 1)))) return rc;
-        if ((rc = upload(S, &D.Mc64, build_compressed<double>(M, dp, 0)))) return rc;
-        if ((rc = upload(S, &D.Mc32, build_compressed<float>(M, dp, 1)))) return rc;
+
     } else {
         D.dp = d;
         int nsl = (d + 63) / 64;
@@ -636,21 +612,27 @@ int qtm_run_range(qtm_ctx* c, int64_t traj_begin, int64_t count, uint64_t seed) 
 
     qtm::LaunchInfo li{};
     HIPCHECK(hipEventRecord(c->ev0, c->stream));
-    int lr;
-    if (S0.sparse) {
-        int cols = c->o.tile_cols > 0 ? c->o.tile_cols : (c->o.precision == QTM_PREC_FP32 ? 4 : 2);
-        lr = qtm::launch_sparse(a, S0.dev, c->o.precision, cols, c->stream, &li);
-    } else {
-        if (qtm::wave_supported(S0.d)) {
-            // one wavefront per 16 trajectories; tile_cols selects waves per block (16..64 columns)
-            lr = qtm::launch_wave(a, S0.dev, c->o.precision, c->o.team_waves, c->stream, &li);
+    // one launch per system, in system order, on the context's stream
+    for (size_t si = 0; si < c->sys.size(); ++si) {
+        const SysHost& Sx = c->sys[si];
+        qtm::RunArgs as = a;
+        as.sys = c->d_sys + si;
+        as.n_sys = 1;
+        int lr;
+        qtm::LaunchInfo lx{};
+        if (Sx.sparse) {
+            int cols = c->o.tile_cols > 0 ? c->o.tile_cols : (c->o.precision == QTM_PREC_FP32 ? 4 : 2);
+            lr = qtm::launch_sparse(as, Sx.dev, c->o.precision, cols, c->stream, &lx);
+        } else if (Sx.team) {
+            lr = qtm::launch_wave(as, Sx.dev, c->o.precision, c->o.team_waves, c->stream, &lx);
         } else {
             int bpc = 0, lds = 0;
-            if (qtm::dense_occupancy(S0.d, c->o.precision, c->o.tile_cols, &bpc, &lds)) bpc = 1;
-            lr = qtm::launch_dense(a, S0.dev, S0.d, c->o.precision, bpc, c->stream, &li);
+            if (qtm::dense_occupancy(Sx.d, c->o.precision, c->o.tile_cols, &bpc, &lds)) bpc = 1;
+            lr = qtm::launch_dense(as, Sx.dev, Sx.d, c->o.precision, bpc, c->stream, &lx);
         }
+        if (lr) return fail(QTM_E_DEVICE, "kernel launch failed for system %zu (%d): %s", si, lr, hipGetErrorString(hipGetLastError()));
+        if (si == 0) li = lx;
     }
-    if (lr) return fail(QTM_E_DEVICE, "kernel launch failed (%d): %s", lr, hipGetErrorString(hipGetLastError()));
     HIPCHECK(hipEventRecord(c->ev1, c->stream));
     for (auto& S : c->sys)
         if (qtm::launch_average(S.dev, (double*)S.sum.p, (double*)S.sumsq.p, c->stream))

@@ -31,8 +31,6 @@ struct DevSystem {
     // right-hand-side operator M = -i H_eff
     const double* Mfrag;       // dense: (2dp)^2 doubles in MFMA A-fragment order
     const float* Mfrag32;      // same, rounded to FP32
-    const double* Mc64;        // dense, d <= 64: complex-compressed fragments for the team kernel
-    const float* Mc32;         // same layout for FP32 products
     const int* sl_off;         // sparse: sliced ELL, 64-row slices; entry offset of each slice
     const int* sl_w;           // width of each slice
     const int* sl_col;         // [slice entries], column-major inside a slice
