@@ -7,11 +7,16 @@ alpha = 2 with the atom excited, t in [0, 50] with 501 output times, 10,000
 trajectories, rtol 1e-6, atol 1e-8.  Inputs are synthetic and resident on the
 device before timing starts.
 
-Forms: "plain" (FP64 products, one block per 16 trajectories, starting-step
-rule), and the headline "learned+batched+mixed" (FP32 MFMA products with FP64
-state/norms/root finding/averages, persistent blocks with slot refill, and
-the trained step proposal).  ``value`` is the headline form's throughput; the
-plain form's is reported beside it.
+Forms: "plain" (FP64 products, the starting-step rule at every segment start)
+and the headline "learned+batched+mixed" (FP32 products with FP64 state,
+norms, root finding and averages, persistent teams with slot refill, and the
+step proposal trained on the device from segment records of the plain
+solver).  Both run with the team shape picked by the autotuner.  ``value`` is
+the headline form's throughput; the plain form's is reported beside it.
+
+The roofline entry is for the trajectory kernel (traj_team_kernel): algorithmic
+FLOPs = attempted steps x (6 complex products 8 d^2 + 32 vector operations 4 d),
+divided by the kernel time that HIP events record on the launch stream.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--forms plain,best]
 """
@@ -49,18 +54,24 @@ def feature_ops(N: int = 20):
     return ops
 
 
-def train_proposal(qtm, system, n_traj_data: int = 170_000, epochs: int = 8, seed: int = 1):
-    """Trains the step proposal on segment records produced by the plain GPU solver."""
+def _neutral_params(qtm):
+    p = np.zeros(qtm.MLP_NTOTAL, dtype=np.float32)
+    p[-16:] = 1.0
+    return p
+
+
+def training_data(qtm, system, n_traj_data: int = 170_000, seed: int = 1):
+    """Segment records of the plain FP64 GPU solver -> (features, targets).
+
+    Targets: log of the controller's step after the segment's first accepted
+    step, log of the realised jump delay and the censoring flag."""
     f_ops = feature_ops()
     gen = qtm.create_system(system, qtm.Opts(seg_cap=16, form=qtm.FORM_BATCHED))
+    gen.set_proposal(_neutral_params(qtm), f_ops)      # installs the feature operators
     feats, tgts = [], []
-    chunk = 20_000
-    done = 0
+    chunk, done = 20_000, 0
     while done < n_traj_data:
         cnt = min(chunk, n_traj_data - done)
-        # feature operators must be installed for the records to carry them
-        gen.set_proposal(_neutral_params(qtm), f_ops)
-        gen.opts.form = qtm.FORM_BATCHED
         gen.run_range(done, cnt, seed)
         seg = gen.segments().reshape(-1, qtm.SEG_REC)
         seg = seg[(seg[:, 19] > 0) & (seg[:, 17] > 0)]
@@ -69,15 +80,7 @@ def train_proposal(qtm, system, n_traj_data: int = 170_000, epochs: int = 8, see
         tgts.append(np.stack([np.log(seg[:, 17]), np.log(np.maximum(tau, 1e-12)), seg[:, 18]], 1))
         done += cnt
     gen.destroy()
-    F = np.concatenate(feats).astype(np.float32)
-    T = np.concatenate(tgts).astype(np.float32)
-    return F, T, f_ops
-
-
-def _neutral_params(qtm):
-    p = np.zeros(qtm.MLP_NTOTAL, dtype=np.float32)
-    p[-16:] = 1.0
-    return p
+    return np.concatenate(feats).astype(np.float32), np.concatenate(tgts).astype(np.float32), f_ops
 
 
 def time_form(qtm, system, opts, steps, warmup, seed0=0, proposal=None):
@@ -87,8 +90,8 @@ def time_form(qtm, system, opts, steps, warmup, seed0=0, proposal=None):
         ctx.set_proposal(*proposal)
     for i in range(warmup):
         ctx.run(NTRAJ, seed0 + 1000 + i)
-    torch.cuda.synchronize()
     kms, units, acc, rej, seg = [], 0, 0, 0, 0
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
         ctx.run(NTRAJ, seed0 + i)
@@ -100,11 +103,10 @@ def time_form(qtm, system, opts, steps, warmup, seed0=0, proposal=None):
         seg += st["segments"]
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    mean, var = ctx.expect()
     info = ctx.stats()
     ctx.destroy()
     return dict(wall=wall, kernel_ms=float(np.mean(kms)), steps_per_run=units / steps, acc=acc / steps,
-                rej=rej / steps, segments=seg / steps, mean=mean, var=var, launch=info)
+                rej=rej / steps, segments=seg / steps, launch=info)
 
 
 def cpu_baseline(system, target_s: float = 12.0):
@@ -119,7 +121,8 @@ def cpu_baseline(system, target_s: float = 12.0):
     oracle.run(system, n, seed=0, nthreads=threads)
     dt = time.perf_counter() - t0
     return {"value": n / dt, "unit": "trajectories/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n} of the {NTRAJ} trajectories (same system, seed 0), FP64 C++ oracle, OpenMP"}
+            "sample": f"trajectories 0..{n - 1} of the same workload (seed 0), FP64 C++ oracle, "
+                      f"{threads} OpenMP threads, {dt:.1f} s"}
 
 
 def main():
@@ -130,6 +133,7 @@ def main():
     ap.add_argument("--forms", default="plain,best")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--tune-cache", default=None, help="JSON file for the autotuner's choices")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: trajectories are independent and the multi-GPU path "
@@ -137,6 +141,7 @@ def main():
         sys.exit(2)
     import torch
     import paper_1810_03047_amd as qtm
+    from paper_1810_03047_amd import autotune
     import workloads as w
 
     if not torch.cuda.is_available():
@@ -145,22 +150,38 @@ def main():
     system = w.jaynes_cummings()
     d = system.dim
     forms = a.forms.split(",")
-    res = {}
+    res, tuned = {}, {}
     if "plain" in forms:
-        res["plain"] = time_form(qtm, system, qtm.Opts(precision=qtm.PREC_FP64), a.steps, a.warmup)
-    best_name = None
+        o = qtm.Opts(precision=qtm.PREC_FP64)
+        tw = autotune.pick_team_waves(system, o, NTRAJ, cache_path=a.tune_cache)
+        tuned["plain"] = tw
+        o.team_waves = tw["team_waves"]
+        print(f"[bench] plain: team_waves {tw}", file=sys.stderr, flush=True)
+        res["plain"] = time_form(qtm, system, o, a.steps, a.warmup)
+    best_name, train_info = None, None
     if "best" in forms:
         proposal = None
         form = qtm.FORM_BATCHED
         if not a.no_learned:
-            F, T, f_ops = train_proposal(qtm, system)
+            t0 = time.perf_counter()
+            F, T, f_ops = training_data(qtm, system)
+            t1 = time.perf_counter()
             trainer = qtm.create_system(system, qtm.Opts())
-            trainer.train_proposal(F, T, epochs=8, batch=4096, lr=2e-3, seed=0)
+            losses = trainer.train_proposal(F, T, epochs=8, batch=4096, lr=2e-3, seed=0)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
             proposal = (trainer.get_proposal(), f_ops)
             trainer.destroy()
             form |= qtm.FORM_LEARNED
-        res["best"] = time_form(qtm, system, qtm.Opts(precision=qtm.PREC_FP32, form=form), a.steps, a.warmup,
-                                proposal=proposal)
+            train_info = {"samples": int(len(F)), "epochs": 8, "data_s": t1 - t0, "train_s": t2 - t1,
+                          "loss_first": float(losses[0]), "loss_last": float(losses[-1])}
+            print(f"[bench] proposal trained: {train_info}", file=sys.stderr, flush=True)
+        o = qtm.Opts(precision=qtm.PREC_FP32, form=form)
+        tw = autotune.pick_team_waves(system, o, NTRAJ, cache_path=a.tune_cache, proposal=proposal)
+        tuned["best"] = tw
+        o.team_waves = tw["team_waves"]
+        print(f"[bench] best: team_waves {tw}", file=sys.stderr, flush=True)
+        res["best"] = time_form(qtm, system, o, a.steps, a.warmup, proposal=proposal)
         best_name = "learned+batched+mixed" if proposal is not None else "batched+mixed"
     head = res.get("best") or res["plain"]
     prec = "fp32" if "best" in res else "fp64"
@@ -174,20 +195,24 @@ def main():
         "dtype": "f32 products, f64 state" if prec == "fp32" else "f64",
         "data": "synthetic",
         "config": {"workload": "jaynes_cummings N=20 x atom (d=40, dense), g=1, kappa=0.1, gamma=0.05, alpha=2, "
-                               "t in [0,50] (501 points), rtol 1e-6, atol 1e-8",
+                               "t in [0,50] (501 points), rtol 1e-6, atol 1e-8, 10000 trajectories",
                    "ntraj": NTRAJ, "form": best_name or "plain", "parallelism": "trajectories (1 GPU)"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK[prec], "unit": "TFLOP/s",
                      "frac": achieved / PEAK[prec], "traffic": None,
-                     "kernel": "traj_dense_kernel", "kernel_ms": head["kernel_ms"],
+                     "kernel": "traj_team_kernel", "kernel_ms": head["kernel_ms"],
                      "flop_per_traj_step": jcm_flops_per_step(d), "traj_steps_per_launch": head["steps_per_run"]},
+        "tuned_team_waves": {k: v["team_waves"] for k, v in tuned.items()},
     }
+    if train_info:
+        line["training"] = train_info
     if "plain" in res and "best" in res:
         p = res["plain"]
         line["plain"] = {"value": NTRAJ * a.steps / p["wall"], "kernel_ms": p["kernel_ms"],
                          "traj_steps_per_launch": p["steps_per_run"],
                          "tflops": p["steps_per_run"] * jcm_flops_per_step(d) / (p["kernel_ms"] * 1e-3) / 1e12}
         line["speedup_vs_plain"] = line["value"] / line["plain"]["value"]
-        line["steps_per_traj"] = {"plain": p["steps_per_run"] / NTRAJ, "best": head["steps_per_run"] / NTRAJ}
+        line["per_traj"] = {k: {"accepted": r["acc"] / NTRAJ, "rejected": r["rej"] / NTRAJ,
+                                "segments": r["segments"] / NTRAJ} for k, r in res.items()}
     if not a.no_cpu:
         line["cpu_baseline"] = cpu_baseline(system)
     print(json.dumps(line), flush=True)

@@ -168,6 +168,35 @@ std::vector<T> build_frag(const HCsr& M, int dp, int prec) {
     return f;
 }
 
+// Team-kernel fragments [RT][RT][64][4]: A-fragment of output tile rt and K-block
+// (source tile s, slot i), whose K index at lane group g is the real-embedded row
+// that lane group g holds in accumulator slot i of tile s (FP64: 16 s + g + 4 i,
+// FP32: 16 s + 4 g + i), so the state feeds the matrix cores in place.
+template <class T>
+std::vector<T> build_frag_team(const HCsr& M, int dp, int prec) {
+    const int n = 2 * dp, RT = n / 16;
+    std::vector<double> real((size_t)n * n, 0.0);
+    for (int i = 0; i < M.d; ++i)
+        for (int p = M.rp[i]; p < M.rp[i + 1]; ++p) {
+            int j = M.ci[p];
+            double re = M.v[p].real(), im = M.v[p].imag();
+            real[(size_t)row_of(i, 0, prec) * n + row_of(j, 0, prec)] += re;
+            real[(size_t)row_of(i, 0, prec) * n + row_of(j, 1, prec)] += -im;
+            real[(size_t)row_of(i, 1, prec) * n + row_of(j, 0, prec)] += im;
+            real[(size_t)row_of(i, 1, prec) * n + row_of(j, 1, prec)] += re;
+        }
+    std::vector<T> f((size_t)n * n);
+    for (int rt = 0; rt < RT; ++rt)
+        for (int s = 0; s < RT; ++s)
+            for (int l = 0; l < 64; ++l)
+                for (int i = 0; i < 4; ++i) {
+                    const int g = l >> 4;
+                    const int col = prec == 0 ? 16 * s + g + 4 * i : 16 * s + 4 * g + i;
+                    f[(((size_t)rt * RT + s) * 64 + l) * 4 + i] = (T)real[(size_t)(16 * rt + (l & 15)) * n + col];
+                }
+    return f;
+}
+
 struct DevBuf {
     void* p = nullptr;
     size_t n = 0;
@@ -181,7 +210,7 @@ struct SysHost {
     std::vector<double> tlist;
     std::vector<DevBuf> bufs;          // device allocations owned by the system
     // run outputs
-    DevBuf X, tstat, jt, jc, jn, segs, queue, sum, sumsq;
+    DevBuf X, tstat, jt, jc, jn, segs, queue, sum, sumsq, avg_part;
     long long cap_count = 0;
     std::vector<double> h_sum, h_sumsq;
     long long sum_count = 0;
@@ -199,6 +228,7 @@ struct qtm_ctx {
     unsigned long long* d_counters = nullptr;
     unsigned int* d_cursor = nullptr;
     float* d_mlp = nullptr;            // BF16-rounded weights for inference
+    unsigned short* d_mlpf = nullptr;  // the same weights as BF16 matrix-core fragments
     std::vector<float> mlp_master;     // FP32 master weights
     bool have_mlp = false;
     bool ran = false;
@@ -287,8 +317,13 @@ int setup_system(SysHost& S, const qtm_system& in, int idx, const qtm_opts& o, b
         int dp = (d + 7) / 8 * 8;
         D.dp = dp;
         D.rt = 2 * dp / 16;
-        if ((rc = upload(S, &D.Mfrag, build_frag<double>(M, dp, 0)))) return rc;
-        if ((rc = upload(S, &D.Mfrag32, build_frag<float>(M, dp, 1)))) return rc;
+        if (S.team) {
+            if ((rc = upload(S, &D.Mfrag, build_frag_team<double>(M, dp, 0)))) return rc;
+            if ((rc = upload(S, &D.Mfrag32, build_frag_team<float>(M, dp, 1)))) return rc;
+        } else {
+            if ((rc = upload(S, &D.Mfrag, build_frag<double>(M, dp, 0)))) return rc;
+            if ((rc = upload(S, &D.Mfrag32, build_frag<float>(M, dp, 1)))) return rc;
+        }
 
     } else {
         D.dp = d;
@@ -449,6 +484,33 @@ void working_copy(const std::vector<float>& master, std::vector<float>& q) {
     for (int i = 0; i < nW3; ++i) q[oW3 + i] = bf16_round(q[oW3 + i]);
 }
 
+// Matrix-core fragments of the BF16 working copy (FP32 16x16x4 A-operands, 4 per
+// lane and group, stored as BF16): groups 0..3 layer 1 (output tile rt, K-block
+// kb = feature 4 g + kb at lane group g), 4..19 layer 2 (rt, source tile s: slot i
+// = hidden unit 16 s + 4 g + i, the accumulator layout), 20..23 layer 3 (rows
+// past the 3 outputs are zero).
+std::vector<uint16_t> mlp_fragments(const std::vector<float>& q) {
+    const int NF = qtm::kNF, NH = qtm::kNH, NO = qtm::kNO;
+    const float* W1 = q.data();
+    const float* W2 = W1 + NH * NF + NH;
+    const float* W3 = W2 + NH * NH + NH;
+    auto bits = [](float x) { uint32_t u; std::memcpy(&u, &x, 4); return (uint16_t)(u >> 16); };
+    std::vector<uint16_t> f(qtm::kMlpFrag, 0);
+    for (int l = 0; l < 64; ++l) {
+        const int m = l & 15, g = l >> 4;
+        for (int i = 0; i < 4; ++i) {
+            for (int rt = 0; rt < 4; ++rt) {
+                f[((size_t)rt * 64 + l) * 4 + i] = bits(W1[(16 * rt + m) * NF + 4 * g + i]);
+                for (int s2 = 0; s2 < 4; ++s2)
+                    f[((size_t)(4 + 4 * rt + s2) * 64 + l) * 4 + i] = bits(W2[(16 * rt + m) * NH + 16 * s2 + 4 * g + i]);
+            }
+            for (int s2 = 0; s2 < 4; ++s2)
+                f[((size_t)(20 + s2) * 64 + l) * 4 + i] = m < NO ? bits(W3[m * NH + 16 * s2 + 4 * g + i]) : 0;
+        }
+    }
+    return f;
+}
+
 struct DevScratch {
     std::vector<void*> ptrs;
     ~DevScratch() { for (void* p : ptrs) if (p) (void)hipFree(p); }
@@ -521,7 +583,8 @@ static int create_common(qtm_ctx** out, int32_t n_sys, const qtm_system* sys, co
         hipMalloc(&c->d_fail, sizeof(long long)) != hipSuccess ||
         hipMalloc(&c->d_counters, 4 * sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc(&c->d_cursor, sizeof(unsigned int)) != hipSuccess ||
-        hipMalloc(&c->d_mlp, sizeof(float) * qtm::kNTotal) != hipSuccess) {
+        hipMalloc(&c->d_mlp, sizeof(float) * qtm::kNTotal) != hipSuccess ||
+        hipMalloc(&c->d_mlpf, sizeof(unsigned short) * qtm::kMlpFrag) != hipSuccess) {
         qtm_destroy(c);
         return fail(QTM_E_NOMEM, "device allocation failed");
     }
@@ -566,6 +629,7 @@ int qtm_run_range(qtm_ctx* c, int64_t traj_begin, int64_t count, uint64_t seed) 
         if ((rc = ensure_buf(S.queue, sizeof(unsigned long long)))) return rc;
         if ((rc = ensure_buf(S.sum, sizeof(double) * 2 * m))) return rc;
         if ((rc = ensure_buf(S.sumsq, sizeof(double) * m))) return rc;
+        if ((rc = ensure_buf(S.avg_part, sizeof(double) * qtm::average_part_size((int)m, count)))) return rc;
         HIPCHECK(hipMemsetAsync(S.queue.p, 0, sizeof(unsigned long long), c->stream));
         HIPCHECK(hipMemsetAsync(S.X.p, 0, sizeof(double2) * m * count, c->stream));
         HIPCHECK(hipMemsetAsync(S.tstat.p, 0, sizeof(int) * 4 * count, c->stream));
@@ -600,6 +664,7 @@ int qtm_run_range(qtm_ctx* c, int64_t traj_begin, int64_t count, uint64_t seed) 
     a.seg_cap = segc;
     a.learned = (c->o.form & QTM_FORM_LEARNED) ? 1 : 0;
     a.mlp = c->d_mlp;
+    a.mlpf = c->d_mlpf;
     a.fail = c->d_fail;
     a.counters = c->d_counters;
     a.tile_cols = c->o.tile_cols;
@@ -635,7 +700,7 @@ int qtm_run_range(qtm_ctx* c, int64_t traj_begin, int64_t count, uint64_t seed) 
     }
     HIPCHECK(hipEventRecord(c->ev1, c->stream));
     for (auto& S : c->sys)
-        if (qtm::launch_average(S.dev, (double*)S.sum.p, (double*)S.sumsq.p, c->stream))
+        if (qtm::launch_average(S.dev, (double*)S.avg_part.p, (double*)S.sum.p, (double*)S.sumsq.p, c->stream))
             return fail(QTM_E_DEVICE, "average kernel launch failed");
     HIPCHECK(hipStreamSynchronize(c->stream));
     float ms = 0.f;
@@ -766,6 +831,10 @@ int qtm_set_proposal(qtm_ctx* c, const float* params, int32_t n_params, const qt
     std::vector<float> q;
     working_copy(c->mlp_master, q);
     HIPCHECK(hipMemcpy(c->d_mlp, q.data(), sizeof(float) * qtm::kNTotal, hipMemcpyHostToDevice));
+    {
+        std::vector<uint16_t> fr = mlp_fragments(q);
+        HIPCHECK(hipMemcpy(c->d_mlpf, fr.data(), sizeof(uint16_t) * fr.size(), hipMemcpyHostToDevice));
+    }
     for (auto& S : c->sys) {
         const int d = S.d;
         std::vector<double> fd((size_t)12 * d, 0.0);
@@ -872,6 +941,10 @@ int qtm_train_proposal(qtm_ctx* c, const float* feat, const float* tgt, int64_t 
     HIPCHECK(hipMemcpy(c->mlp_master.data(), dMaster, sizeof(float) * qtm::kNTotal, hipMemcpyDeviceToHost));
     working_copy(c->mlp_master, q);
     HIPCHECK(hipMemcpy(c->d_mlp, q.data(), sizeof(float) * qtm::kNTotal, hipMemcpyHostToDevice));
+    {
+        std::vector<uint16_t> fr = mlp_fragments(q);
+        HIPCHECK(hipMemcpy(c->d_mlpf, fr.data(), sizeof(uint16_t) * fr.size(), hipMemcpyHostToDevice));
+    }
     return QTM_OK;
 }
 
@@ -881,13 +954,14 @@ void qtm_destroy(qtm_ctx* c) {
     for (auto& S : c->sys) {
         for (auto& b : S.bufs) if (b.p) (void)hipFree(b.p);
         free_buf(S.X); free_buf(S.tstat); free_buf(S.jt); free_buf(S.jc); free_buf(S.jn);
-        free_buf(S.segs); free_buf(S.queue); free_buf(S.sum); free_buf(S.sumsq);
+        free_buf(S.segs); free_buf(S.queue); free_buf(S.sum); free_buf(S.sumsq); free_buf(S.avg_part);
     }
     if (c->d_sys) (void)hipFree(c->d_sys);
     if (c->d_fail) (void)hipFree(c->d_fail);
     if (c->d_counters) (void)hipFree(c->d_counters);
     if (c->d_cursor) (void)hipFree(c->d_cursor);
     if (c->d_mlp) (void)hipFree(c->d_mlp);
+    if (c->d_mlpf) (void)hipFree(c->d_mlpf);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     delete c;

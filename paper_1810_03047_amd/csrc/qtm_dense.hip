@@ -46,16 +46,43 @@ __global__ void __launch_bounds__(512) traj_dense_kernel(RunArgs a, int lds_m) {
     if (threadIdx.x == 0) atomicAdd(&a.counters[0], B.passes);
 }
 
-// Trajectory average in index order: one thread per (observable, time).
-__global__ void average_kernel(const double2* X, long long count, int m, double* sum, double* sumsq) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+// Trajectory average in a fixed order (independent of scheduling): chunk c of
+// the trajectories is summed in index order by one thread per (observable,
+// time) point, then the chunks are summed in chunk order.  part = [3][nchunk][m].
+__global__ void average_partial_kernel(const double2* X, long long count, int m, int nchunk, long long per,
+                                       double* part) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
     if (i >= m) return;
+    const long long q0 = (long long)c * per;
+    const long long q1 = q0 + per < count ? q0 + per : count;
     double sr = 0.0, si = 0.0, s2 = 0.0;
-    for (long long q = 0; q < count; ++q) {
-        double2 x = X[q * m + i];
+    for (long long q = q0; q < q1; ++q) {
+        const double2 x = X[q * m + i];
         sr += x.x; si += x.y; s2 += x.x * x.x;
     }
+    part[((size_t)0 * nchunk + c) * m + i] = sr;
+    part[((size_t)1 * nchunk + c) * m + i] = si;
+    part[((size_t)2 * nchunk + c) * m + i] = s2;
+}
+
+__global__ void average_final_kernel(const double* part, int nchunk, int m, double* sum, double* sumsq) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    double sr = 0.0, si = 0.0, s2 = 0.0;
+    for (int c = 0; c < nchunk; ++c) {
+        sr += part[((size_t)0 * nchunk + c) * m + i];
+        si += part[((size_t)1 * nchunk + c) * m + i];
+        s2 += part[((size_t)2 * nchunk + c) * m + i];
+    }
     sum[2 * i] = sr; sum[2 * i + 1] = si; sumsq[i] = s2;
+}
+
+static int average_chunks(int m, long long count) {
+    long long n = (65536 + m - 1) / m;           // about 64k threads in the first pass
+    if (n > 256) n = 256;
+    if (n > count) n = count;
+    return n < 1 ? 1 : (int)n;
 }
 
 // ------------------------------------------------------------------ host launchers
@@ -131,9 +158,16 @@ int launch_dense(const RunArgs& a, const DevSystem& s0, int max_d, int prec, int
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
-int launch_average(const DevSystem& s, double* sum, double* sumsq, hipStream_t st) {
-    int m = s.n_e * s.n_t;
-    hipLaunchKernelGGL(average_kernel, dim3((m + 255) / 256), dim3(256), 0, st, (const double2*)s.X, s.count, m, sum, sumsq);
+size_t average_part_size(int m, long long count) { return (size_t)3 * average_chunks(m, count) * m; }
+
+int launch_average(const DevSystem& s, double* part, double* sum, double* sumsq, hipStream_t st) {
+    const int m = s.n_e * s.n_t;
+    const int nchunk = average_chunks(m, s.count);
+    const long long per = (s.count + nchunk - 1) / nchunk;
+    hipLaunchKernelGGL(average_partial_kernel, dim3((m + 255) / 256, nchunk), dim3(256), 0, st, (const double2*)s.X,
+                       s.count, m, nchunk, per, part);
+    hipLaunchKernelGGL(average_final_kernel, dim3((m + 255) / 256), dim3(256), 0, st, (const double*)part, nchunk, m,
+                       sum, sumsq);
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 

@@ -13,6 +13,7 @@ constexpr int kNF = 16, kNH = 64, kNO = 3;   // proposal network 16 -> 64 -> 64 
 constexpr int kNParam = kNH * kNF + kNH + kNH * kNH + kNH + kNO * kNH + kNO;  // 5443
 constexpr int kNTotal = kNParam + 2 * kNF;                                      // + mean, scale
 constexpr int kSegRec = 20;      // floats per segment record
+constexpr int kMlpFrag = 24 * 64 * 4;   // BF16 A-fragments of the proposal: 24 groups x 64 lanes x 4
 
 // Column (trajectory slot) states.
 enum : int { ST_EMPTY = 0, ST_NEW = 1, ST_NEEDK1 = 2, ST_NEEDF1 = 3, ST_PROBED = 4, ST_STEP = 5 };
@@ -29,7 +30,8 @@ struct DevSystem {
     int e_fmt[kMaxE];          // 1 CSR, 2 diagonal
     int e_doff[kMaxE];         // diagonal values offset into e_val
     // right-hand-side operator M = -i H_eff
-    const double* Mfrag;       // dense: (2dp)^2 doubles in MFMA A-fragment order
+    const double* Mfrag;       // dense: (2dp)^2 doubles in MFMA A-fragment order (block kernel:
+                               // [RT][KB][64]; team kernel: [RT][RT][64][4], permuted columns)
     const float* Mfrag32;      // same, rounded to FP32
     const int* sl_off;         // sparse: sliced ELL, 64-row slices; entry offset of each slice
     const int* sl_w;           // width of each slice
@@ -71,6 +73,7 @@ struct RunArgs {
     int jcap, seg_cap;
     int learned;
     const float* mlp;          // [kNTotal] weights (BF16-rounded values), biases, mean, scale
+    const unsigned short* mlpf;  // [kMlpFrag] BF16 weight fragments for the matrix-core evaluation
     long long* fail;           // smallest failing global trajectory index (LLONG_MAX: none)
     unsigned long long* counters;  // [4]: passes, rhs column-evaluations, cycles, unused
     long long max_cycles;      // failsafe bound on block cycles
@@ -83,7 +86,10 @@ struct LaunchInfo { int blocks, threads, lds, cols, shape; };
 int launch_dense(const RunArgs& a, const DevSystem& s0, int max_d, int prec, int blocks_per_cu,
                  hipStream_t st, LaunchInfo* info);
 int launch_sparse(const RunArgs& a, const DevSystem& s0, int prec, int cols, hipStream_t st, LaunchInfo* info);
-int launch_average(const DevSystem& s, double* sum, double* sumsq, hipStream_t st);
+// fixed-order trajectory average: partial sums over chunks of trajectories, then
+// the chunks in order; part holds average_part_size(m) doubles
+size_t average_part_size(int m, long long count);
+int launch_average(const DevSystem& s, double* part, double* sum, double* sumsq, hipStream_t st);
 int dense_occupancy(int max_d, int prec, int tile_cols, int* blocks_per_cu, int* lds);
 // proposal network (qtm_mlp.hip)
 int launch_mlp_grad(const float* P, const float* feat, const float* tgt, const int* perm, long long base, int n,

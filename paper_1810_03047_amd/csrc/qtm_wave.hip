@@ -5,9 +5,12 @@
 // state stays in registers.  A block holds one team, or up to four single-wave
 // teams that share the operator in LDS.
 //
-// The product K = M W runs on the matrix cores (16x16x4 MFMA, FP64 or FP32):
-// W is staged in the team's LDS tile and M's A-fragments (real embedding) are
-// read from LDS, one value per lane and MFMA, prefetched one k-block ahead.
+// The product K = M W runs on the matrix cores (16x16x4 MFMA, FP64 or FP32).
+// The operator's A-fragments (real embedding, in LDS) have their columns
+// permuted so that K-block (source tile s, slot i) is exactly the value each
+// lane keeps in accumulator slot i of its tile s: a single-wave team feeds W
+// to the matrix cores from registers, and larger teams exchange their tiles
+// through LDS in plain lane order.
 //
 // Per-trajectory scalars (t, h, threshold, ...) are replicated on the four lane
 // groups and on the team's waves, which all take identical decisions from
@@ -40,15 +43,15 @@ struct Team {
 
     const DevSystem& S;
     const RunArgs& A;
-    const in_t* Mf;          // LDS: A-fragments of the real-embedded operator [RT][KB][64]
-    in_t* Wb;                // LDS: operand tile [2dp][16]
+    const in_t* Mf;          // LDS: A-fragments [RT][RT][64][4] (output tile, source tile, lane, slot)
+    in_t* Wb;                // LDS: operand tiles [RT][64][4] (teams of several waves)
     double2* St;             // alias of Wb: complex staging [dp][16]
     double* Xb;              // LDS: team reduction exchange [NWT][16][kXV]
     unsigned long long* Ib;  // LDS: trajectory hand-out [16]
     int* Fb;                 // LDS: team flags [4]
     const double2* Od;       // LDS copy of the diagonal observables [n_e][d] (when od_lds)
     int od_lds;
-    int lane, lg, c16, wv, RT, KB, d, dp;
+    int lane, lg, c16, wv, RT, d, dp, q0;
 
     // per-lane trajectory state (identical on every lane of a column, on every wave)
     double t, h, h0, d1, r, u, tseg, tb, fac, th, oth, tnext;
@@ -59,19 +62,26 @@ struct Team {
 
     double2 y[NE], yn[NE];
     kv_t k[7][NE];
-    double2 es[NE], ds[NE];  // sum_j e_j k_j and sum_j d_j k_j over stages 1..6
+    kv_t es[NE], ds[NE];     // sum_j e_j k_j and sum_j d_j k_j over stages 1..6 (product precision)
 
     QTM_DI Team(const DevSystem& s, const RunArgs& a) : S(s), A(a) {}
+
+    // acc + c k in the product precision
+    QTM_DI static double2 kfma(double c, const double2& k, const double2& acc) { return cfma(c, k, acc); }
+    QTM_DI static float2 kfma(double c, const float2& k, const float2& acc) {
+        return make_float2(fmaf((float)c, k.x, acc.x), fmaf((float)c, k.y, acc.y));
+    }
 
     QTM_DI void team_sync() const {
         if (NWT > 1) __syncthreads();
         else wave_sync();
     }
-    QTM_DI int qraw(int e) const {
-        int rt = wv * T + (e >> 1);
-        return rt < RT ? RowMap<PREC>::comp(rt, lg, e & 1) : -1;
-    }
-    QTM_DI int comp(int e) const { int q = qraw(e); return q < d ? q : -1; }
+    // Component held in element e of a lane: q0 + cst(e), q0 = 8 T wv + lg (FP64,
+    // output rows lg + 4 i) or 8 T wv + 2 lg (FP32, rows 4 lg + i); elements
+    // 2 tt and 2 tt + 1 are accumulator slots (0, 1) and (2, 3) of tile tt.
+    // Components at or past d (padding, or tiles past RT) are invalid.
+    static constexpr int cst(int e) { return PREC == 0 ? 8 * (e >> 1) + 4 * (e & 1) : 8 * (e >> 1) + (e & 1); }
+    QTM_DI int comp(int e) const { int q = q0 + cst(e); return q < d ? q : -1; }
 
     // team-wide per-column sums of NV values (NV <= kXV), identical on every lane
     template <int NV> QTM_DI void tsum(double (&p)[NV]) {
@@ -106,50 +116,63 @@ struct Team {
     }
 
     // ------------------------------------------------------------ product
-    QTM_DI void put(int e, double2 v) {
-        int q = qraw(e);
-        if (q < 0) return;
-        Wb[RowMap<PREC>::row(q, 0) * 16 + c16] = q < d ? (in_t)v.x : (in_t)0;
-        Wb[RowMap<PREC>::row(q, 1) * 16 + c16] = q < d ? (in_t)v.y : (in_t)0;
+    struct alignas(16) In4 { in_t v[4]; };
+    template <class V> QTM_DI static In4 slots(const V& a, const V& b) {
+        In4 r;
+        r.v[0] = (in_t)a.x; r.v[1] = (in_t)a.y; r.v[2] = (in_t)b.x; r.v[3] = (in_t)b.y;
+        return r;
     }
-    // K = M W for the team's 16 columns (W staged by put()).  A-fragments of the
-    // real-embedded operator are read from LDS (one value per lane and MFMA) and
-    // prefetched one k-block ahead; padded tiles (rt >= RT) read a valid tile and
-    // their results are never used, so the loop has no branches.
-    QTM_DI void product(kv_t (&K)[NE]) {
-        team_sync();
+    // K = M W for the team's 16 columns; W in the lane layout of the state.
+    // Every lane of the team must take part (uniform call).
+    template <class V> QTM_DI void product(const V (&W)[NE], kv_t (&K)[NE]) {
         typename MfmaT<PREC>::acc_t acc[T];
-        const in_t* ap[T];
 #pragma unroll
-        for (int tt = 0; tt < T; ++tt) {
-            acc[tt] = 0;
-            int rt = wv * T + tt;
-            rt = rt < RT ? rt : RT - 1;
-            ap[tt] = Mf + (size_t)rt * KB * 64 + lane;
-        }
-        const in_t* bb = Wb + lg * 16 + c16;
-        in_t bn = bb[0];
-        in_t an[T];
+        for (int tt = 0; tt < T; ++tt) acc[tt] = 0;
+        if constexpr (NWT == 1) {
+            // the lane's own tiles are all source tiles (T == RT)
 #pragma unroll
-        for (int tt = 0; tt < T; ++tt) an[tt] = ap[tt][0];
-        for (int kb = 0; kb < KB; ++kb) {
-            const in_t bc = bn;
-            in_t ac[T];
+            for (int s = 0; s < T; ++s) {
+                const In4 b = slots(W[2 * s], W[2 * s + 1]);
+                In4 av[T];
 #pragma unroll
-            for (int tt = 0; tt < T; ++tt) ac[tt] = an[tt];
-            const int kn = kb + 1 < KB ? kb + 1 : kb;
-            bn = bb[(4 * kn) * 16];
+                for (int tt = 0; tt < T; ++tt) av[tt] = *(const In4*)(Mf + ((size_t)(tt * T + s) * 64 + lane) * 4);
 #pragma unroll
-            for (int tt = 0; tt < T; ++tt) an[tt] = ap[tt][(size_t)kn * 64];
+                for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int tt = 0; tt < T; ++tt) acc[tt] = MfmaT<PREC>::op(ac[tt], bc, acc[tt]);
+                    for (int tt = 0; tt < T; ++tt) acc[tt] = MfmaT<PREC>::op(av[tt].v[i], b.v[i], acc[tt]);
+                __builtin_amdgcn_sched_barrier(0);     // one source tile of fragments in flight at a time
+            }
+        } else {
+            team_sync();                // earlier readers of the operand tiles are done
+#pragma unroll
+            for (int tt = 0; tt < T; ++tt) {
+                const int rt = wv * T + tt;
+                if (rt < RT) *(In4*)(Wb + ((size_t)rt * 64 + lane) * 4) = slots(W[2 * tt], W[2 * tt + 1]);
+            }
+            team_sync();
+            // padded tiles (rt >= RT) multiply a valid tile; their results are never used
+            const in_t* ap[T];
+#pragma unroll
+            for (int tt = 0; tt < T; ++tt) {
+                const int rt = wv * T + tt < RT ? wv * T + tt : RT - 1;
+                ap[tt] = Mf + ((size_t)rt * RT * 64 + lane) * 4;
+            }
+            for (int s = 0; s < RT; ++s) {
+                const In4 b = *(const In4*)(Wb + ((size_t)s * 64 + lane) * 4);
+                In4 av[T];
+#pragma unroll
+                for (int tt = 0; tt < T; ++tt) av[tt] = *(const In4*)(ap[tt] + (size_t)s * 256);
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int tt = 0; tt < T; ++tt) acc[tt] = MfmaT<PREC>::op(av[tt].v[i], b.v[i], acc[tt]);
+            }
         }
 #pragma unroll
         for (int tt = 0; tt < T; ++tt) {
             K[2 * tt + 0] = from_d2<kv_t>(make_double2((double)acc[tt][0], (double)acc[tt][1]));
             K[2 * tt + 1] = from_d2<kv_t>(make_double2((double)acc[tt][2], (double)acc[tt][3]));
         }
-        team_sync();
         ++passes;       // summed into the run counters once, when the team exits
     }
 
@@ -160,7 +183,7 @@ struct Team {
         double2 D = csub(yn[e], y[e]);
         double2 B = csub(cscale(h, to_d2(k[0][e])), D);
         double2 R4 = csub(csub(D, cscale(h, to_d2(k[6][e]))), B);
-        double2 R5 = cscale(h, cfma(dp_d(6), to_d2(k[6][e]), ds[e]));
+        double2 R5 = cscale(h, cfma(dp_d(6), to_d2(k[6][e]), to_d2(ds[e])));
         double t1 = 1.0 - tht;
         double2 in = cadd(R4, cscale(t1, R5));
         in = cadd(B, cscale(tht, in));
@@ -274,7 +297,8 @@ struct Team {
         seg = kk = nacc = nrej = njump = natt = last = rejected = ch = seg_rec = first_acc = 0;
 #pragma unroll
         for (int e = 0; e < NE; ++e) {
-            y[e] = yn[e] = es[e] = ds[e] = make_double2(0.0, 0.0);
+            y[e] = yn[e] = make_double2(0.0, 0.0);
+            es[e] = ds[e] = from_d2<kv_t>(make_double2(0.0, 0.0));
 #pragma unroll
             for (int j = 0; j < 7; ++j) k[j][e] = from_d2<kv_t>(make_double2(0.0, 0.0));
         }
@@ -343,9 +367,7 @@ struct Team {
     // k1 = M y, then the starting step (or the learned proposal)
     QTM_DI void segment_start() {
         kv_t K[NE];
-#pragma unroll
-        for (int e = 0; e < NE; ++e) put(e, y[e]);
-        product(K);
+        product(y, K);
 #pragma unroll
         for (int e = 0; e < NE; ++e)
             if (state == ST_NEEDK1) k[0][e] = K[e];
@@ -414,23 +436,85 @@ struct Team {
             }
             f[12 + n] = (float)(acc / nn);
         }
-        if (on) {
-            f[14] = logf((float)r);
-            f[15] = (float)((t - S.t0) / (S.tend - S.t0));
-            if (A.learned) {
-                float lh = mlp_logh(A.mlp, f);
+        if (!on) {
+#pragma unroll
+            for (int v = 0; v < 14; ++v) f[v] = 0.f;
+        }
+        f[14] = on ? logf((float)r) : 0.f;
+        f[15] = on ? (float)((t - S.t0) / (S.tend - S.t0)) : 0.f;
+        if (A.learned) {
+            const float lh = team_mlp(f);
+            if (on) {
                 // snap to the grid 2^(k/4), k = round(4 log2 h)
                 double hh = exp2_quarter((int)rint(4.0 * ((double)lh / 0.69314718055994530942)));
                 h = fmin(hh, S.tend - t);
                 state = ST_STEP;
             }
-            if (A.seg_cap > 0 && seg_rec < A.seg_cap && lg == 0 && wv == 0) {
-                float* rec = S.segs + ((size_t)traj * A.seg_cap + seg_rec) * kSegRec;
-#pragma unroll
-                for (int v = 0; v < kNF; ++v) rec[v] = f[v];
-                rec[16] = 0.f; rec[17] = -1.f; rec[18] = 1.f; rec[19] = 1.f;
-            }
         }
+        if (on && A.seg_cap > 0 && seg_rec < A.seg_cap && lg == 0 && wv == 0) {
+            float* rec = S.segs + ((size_t)traj * A.seg_cap + seg_rec) * kSegRec;
+#pragma unroll
+            for (int v = 0; v < kNF; ++v) rec[v] = f[v];
+            rec[16] = 0.f; rec[17] = -1.f; rec[18] = 1.f; rec[19] = 1.f;
+        }
+    }
+
+    // Proposal network 16 -> 64 -> 64 -> 3 (GELU) for the team's 16 trajectories
+    // at once on the matrix cores: FP32 16x16x4 MFMA on BF16-valued weights, FP32
+    // activations.  Trajectory = MFMA column.  A layer's hidden units come back in
+    // the accumulator layout (unit 16 s + 4 lg + i in slot i of tile s) and feed
+    // the next layer in place: the weight fragments' columns are permuted to
+    // match.  Layer 1 takes standardised features 4 lg .. 4 lg + 3 from each lane
+    // group.  Returns output 0 (log of the proposed first step) on every lane.
+    // Uniform call: every lane of the wave takes part.
+    QTM_DI float team_mlp(const float (&f)[kNF]) {
+        const float* b1 = A.mlp + kNH * kNF;
+        const float* b2 = b1 + kNH + kNH * kNH;
+        const float* b3 = b2 + kNH + kNO * kNH;
+        const float* mu = b3 + kNO;
+        const float* sd = mu + kNF;
+        const uint2* F = (const uint2*)A.mlpf;          // 4 BF16 values per lane and group
+        auto bf = [](unsigned int w, int hi) { return __uint_as_float(hi ? (w & 0xFFFF0000u) : (w << 16)); };
+        float x[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const float v = lg == 0 ? f[j] : lg == 1 ? f[4 + j] : lg == 2 ? f[8 + j] : f[12 + j];
+            x[j] = (v - mu[4 * lg + j]) / sd[4 * lg + j];
+        }
+        float h1[4][4], h2[4][4];
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) {
+            f4 z = 0;
+            const uint2 wq = F[(size_t)rt * 64 + lane];
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb)
+                z = __builtin_amdgcn_mfma_f32_16x16x4f32(bf(kb < 2 ? wq.x : wq.y, kb & 1), x[kb], z, 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) h1[rt][i] = gelu_f(z[i] + b1[16 * rt + 4 * lg + i]);
+        }
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) {
+            f4 z = 0;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const uint2 wq = F[(size_t)(4 + 4 * rt + s) * 64 + lane];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    z = __builtin_amdgcn_mfma_f32_16x16x4f32(bf(i < 2 ? wq.x : wq.y, i & 1), h1[s][i], z, 0, 0, 0);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) h2[rt][i] = gelu_f(z[i] + b2[16 * rt + 4 * lg + i]);
+        }
+        f4 o = 0;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const uint2 wq = F[(size_t)(20 + s) * 64 + lane];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                o = __builtin_amdgcn_mfma_f32_16x16x4f32(bf(i < 2 ? wq.x : wq.y, i & 1), h2[s][i], o, 0, 0, 0);
+        }
+        // output 0 is row 0: slot 0 of lane group 0
+        return __shfl(o[0] + b3[0], c16);
     }
 
     // stage s (0-based): w = y + sum_j c_j k_j, k_s = M w
@@ -439,6 +523,7 @@ struct Team {
 #pragma unroll
         for (int j = 0; j < 6; ++j) cf[j] = (state == ST_STEP) ? h * dp_a(s, j) : 0.0;
         if (s == 1 && state == ST_NEEDF1) cf[0] = h0;
+        kv_t w[NE];              // the stage input, rounded to the product precision
 #pragma unroll
         for (int e = 0; e < NE; ++e) {
             double2 acc;
@@ -460,22 +545,24 @@ struct Team {
                     }
                 acc = make_double2(y[e].x + (double)inc.x, y[e].y + (double)inc.y);
             }
-            put(e, acc);
-            if (s == 6) {
+            if constexpr (s == 6) {
                 // y_new is the last stage input; fold k1..k6 into the error and
                 // dense-output sums now so that k2..k6 need not live longer
                 yn[e] = acc;
-                double2 se = make_double2(0.0, 0.0), sd = make_double2(0.0, 0.0);
+                kv_t se = from_d2<kv_t>(make_double2(0.0, 0.0)), sd = se;
 #pragma unroll
                 for (int j = 0; j < 6; ++j) {
-                    if (dp_e(j) != 0.0) se = cfma(dp_e(j), to_d2(k[j][e]), se);
-                    if (dp_d(j) != 0.0) sd = cfma(dp_d(j), to_d2(k[j][e]), sd);
+                    if (dp_e(j) != 0.0) se = kfma(dp_e(j), k[j][e], se);
+                    if (dp_d(j) != 0.0) sd = kfma(dp_d(j), k[j][e], sd);
                 }
                 es[e] = se;
                 ds[e] = sd;
+            } else {
+                w[e] = from_d2<kv_t>(acc);
             }
         }
-        product(k[s]);
+        if constexpr (s == 6) product(yn, k[s]);
+        else product(w, k[s]);
     }
 
     QTM_DI void stages() {
@@ -513,7 +600,7 @@ struct Team {
             for (int e = 0; e < NE; ++e) {
                 int q = comp(e);
                 if (q < 0) continue;
-                double2 er = cscale(h, cfma(dp_e(6), to_d2(k[6][e]), es[e]));
+                double2 er = cscale(h, cfma(dp_e(6), to_d2(k[6][e]), to_d2(es[e])));
                 double sc = A.atol + A.rtol * fmax(sqrt(cabs2(y[e])), sqrt(cabs2(yn[e])));
                 p[0] += cabs2(er) / (sc * sc);
                 p[1] += cabs2(yn[e]);
@@ -583,7 +670,7 @@ struct Team {
                 v[1] = csub(yn[e], y[e]);
                 v[2] = csub(cscale(h, to_d2(k[0][e])), v[1]);
                 v[3] = csub(csub(v[1], cscale(h, to_d2(k[6][e]))), v[2]);
-                v[4] = cscale(h, cfma(dp_d(6), to_d2(k[6][e]), ds[e]));
+                v[4] = cscale(h, cfma(dp_d(6), to_d2(k[6][e]), to_d2(ds[e])));
                 int n = 0;
 #pragma unroll
                 for (int a = 0; a < 5; ++a)
@@ -756,7 +843,7 @@ __global__ void __launch_bounds__(NWT == 1 ? 256 : 64 * NWT) traj_team_kernel(Ru
     W.d = S.d;
     W.dp = S.dp;
     W.RT = 2 * S.dp / 16;
-    W.KB = 2 * S.dp / 4;
+    W.q0 = 8 * T * W.wv + (PREC == 0 ? W.lg : 2 * W.lg);
     W.run();
     if ((threadIdx.x & 63) == 0 && W.wv == 0) atomicAdd(&a.counters[0], W.passes);
 }
@@ -772,8 +859,8 @@ static const int kShapes[9][3][2] = {
     {{0, 0}, {0, 0}, {0, 0}},
     {{1, 1}, {0, 0}, {0, 0}},
     {{1, 2}, {2, 1}, {0, 0}},
-    {{1, 3}, {2, 2}, {0, 0}},
-    {{1, 4}, {2, 2}, {0, 0}},
+    {{1, 3}, {2, 2}, {3, 1}},
+    {{1, 4}, {2, 2}, {4, 1}},
     {{1, 5}, {3, 2}, {5, 1}},
     {{1, 6}, {2, 3}, {3, 2}},
     {{1, 7}, {4, 2}, {0, 0}},
@@ -797,6 +884,7 @@ static const void* team_fn(int T, int nwt, int prec) {
     QTM_TEAM_CASE(1, 1) QTM_TEAM_CASE(2, 1) QTM_TEAM_CASE(1, 2) QTM_TEAM_CASE(1, 3) QTM_TEAM_CASE(1, 4)
     QTM_TEAM_CASE(2, 2) QTM_TEAM_CASE(1, 5) QTM_TEAM_CASE(3, 2) QTM_TEAM_CASE(5, 1) QTM_TEAM_CASE(1, 6)
     QTM_TEAM_CASE(2, 3) QTM_TEAM_CASE(1, 7) QTM_TEAM_CASE(4, 2) QTM_TEAM_CASE(1, 8) QTM_TEAM_CASE(2, 4)
+    QTM_TEAM_CASE(3, 1) QTM_TEAM_CASE(4, 1)
 #undef QTM_TEAM_CASE
     return nullptr;
 }
@@ -818,6 +906,7 @@ int wave_supported(int d) {
 int launch_wave(const RunArgs& a, const DevSystem& s0, int prec, int waves_per_team, hipStream_t st, LaunchInfo* info) {
     int dp = s0.dp, rt = 2 * dp / 16, T, nwt;
     if (team_shape(rt, waves_per_team, &T, &nwt)) return -1;
+    if (nwt == 1 && T != rt) return -1;          // a single-wave team holds every source tile
     const void* fn = team_fn(T, nwt, prec);
     if (!fn) return -1;
     // diagonal observables are copied to LDS when every observable is diagonal
