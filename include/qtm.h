@@ -106,6 +106,8 @@ typedef struct {
     double kernel_ms;         /* device time of the trajectory kernel(s) */
     double elapsed_ms;        /* host wall time of qtm_run */
     int32_t blocks, threads, tile_cols, lds_bytes;   /* launch configuration used */
+    int64_t max_team_passes;  /* most product passes of one trajectory team (the launch's critical
+                                 path; team kernel only, 0 for the others) */
 } qtm_stats_t;
 
 /* A system for qtm_create_batch (same meaning as the qtm_create arguments). */

@@ -55,7 +55,8 @@ class _Stats(C.Structure):
     _fields_ = [("ntraj", C.c_int64), ("accepted", C.c_int64), ("rejected", C.c_int64), ("segments", C.c_int64),
                 ("jumps", C.c_int64), ("rhs_evals", C.c_int64), ("passes", C.c_int64), ("failed_traj", C.c_int64),
                 ("kernel_ms", C.c_double), ("elapsed_ms", C.c_double), ("blocks", C.c_int32),
-                ("threads", C.c_int32), ("tile_cols", C.c_int32), ("lds_bytes", C.c_int32)]
+                ("threads", C.c_int32), ("tile_cols", C.c_int32), ("lds_bytes", C.c_int32),
+                ("max_team_passes", C.c_int64)]
 
 
 class _System(C.Structure):

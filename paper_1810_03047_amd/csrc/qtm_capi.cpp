@@ -208,6 +208,7 @@ struct SysHost {
     bool team = false;         // team kernel (dense, d <= 64); otherwise the block dense kernel
     qtm::DevSystem dev{};
     std::vector<double> tlist;
+    std::vector<double> cdiag;         // [n_c][d] diagonal of C_n^dag C_n (valid when dev.c_isdiag)
     std::vector<DevBuf> bufs;          // device allocations owned by the system
     // run outputs
     DevBuf X, tstat, jt, jc, jn, segs, queue, sum, sumsq, avg_part;
@@ -368,6 +369,16 @@ int setup_system(SysHost& S, const qtm_system& in, int idx, const qtm_opts& o, b
             for (size_t p = 0; p < c.ci.size(); ++p) { ci.push_back(c.ci[p]); v.push_back(make_double2(c.v[p].real(), c.v[p].imag())); }
         }
         if (rp.empty()) rp.push_back(0);
+        // C_n^dag C_n is diagonal when no row of C_n has two entries; its diagonal is
+        // sum_k |C_kp|^2 (rows 12 + n of the diagonal table)
+        D.c_isdiag = 1;
+        S.cdiag.assign((size_t)in.n_c * d, 0.0);
+        for (int n = 0; n < in.n_c; ++n)
+            for (int k = 0; k < d; ++k) {
+                const int a = rp[(size_t)n * (d + 1) + k], b = rp[(size_t)n * (d + 1) + k + 1];
+                if (b - a > 1) D.c_isdiag = 0;
+                for (int q = a; q < b; ++q) S.cdiag[(size_t)n * d + ci[q]] += v[q].x * v[q].x + v[q].y * v[q].y;
+            }
         if ((rc = upload(S, &D.c_rp, rp))) return rc;
         if ((rc = upload(S, &D.c_ci, ci))) return rc;
         if ((rc = upload(S, &D.c_val, v))) return rc;
@@ -410,7 +421,8 @@ int setup_system(SysHost& S, const qtm_system& in, int idx, const qtm_opts& o, b
         for (int i = 0; i < d; ++i) p0[i] = make_double2(in.psi0[2 * i], in.psi0[2 * i + 1]);
         if ((rc = upload(S, &D.psi0, p0))) return rc;
         if ((rc = upload(S, &D.tlist, S.tlist))) return rc;
-        std::vector<double> fd((size_t)12 * d, 0.0);
+        std::vector<double> fd((size_t)(12 + in.n_c) * d, 0.0);
+        std::copy(S.cdiag.begin(), S.cdiag.end(), fd.begin() + (size_t)12 * d);
         if ((rc = upload(S, &D.f_diag, fd))) return rc;
     }
     (void)o;
@@ -695,6 +707,8 @@ int qtm_run_range(qtm_ctx* c, int64_t traj_begin, int64_t count, uint64_t seed) 
             if (qtm::dense_occupancy(Sx.d, c->o.precision, c->o.tile_cols, &bpc, &lds)) bpc = 1;
             lr = qtm::launch_dense(as, Sx.dev, Sx.d, c->o.precision, bpc, c->stream, &lx);
         }
+        if (Sx.team && lr == -1) return fail(QTM_E_INVAL, "system %zu: no team shape with %d waves for dimension %d", si, c->o.team_waves, Sx.d);
+        if (Sx.team && lr == -2) return fail(QTM_E_INVAL, "system %zu: the team shape does not fit in LDS (dimension %d)", si, Sx.d);
         if (lr) return fail(QTM_E_DEVICE, "kernel launch failed for system %zu (%d): %s", si, lr, hipGetErrorString(hipGetLastError()));
         if (si == 0) li = lx;
     }
@@ -726,6 +740,7 @@ int qtm_run_range(qtm_ctx* c, int64_t traj_begin, int64_t count, uint64_t seed) 
         S.sum_count = count;
     }
     st.passes = (int64_t)ctrs[0];
+    st.max_team_passes = (int64_t)ctrs[2];
     st.rhs_evals = (int64_t)ctrs[0] * li.cols;
     st.failed_traj = failv == LLONG_MAX ? -1 : failv;
     st.kernel_ms = ms;
@@ -837,7 +852,8 @@ int qtm_set_proposal(qtm_ctx* c, const float* params, int32_t n_params, const qt
     }
     for (auto& S : c->sys) {
         const int d = S.d;
-        std::vector<double> fd((size_t)12 * d, 0.0);
+        std::vector<double> fd((size_t)(12 + S.n_c) * d, 0.0);
+        std::copy(S.cdiag.begin(), S.cdiag.end(), fd.begin() + (size_t)12 * d);
         for (int f = 0; f < n_f; ++f) {
             if (f_ops[f].fmt != QTM_FMT_DIAG || f_ops[f].dim != d || !f_ops[f].val)
                 return fail(QTM_E_INVAL, "feature operator %d must be diagonal of dimension %d", f, d);

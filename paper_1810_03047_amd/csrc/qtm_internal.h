@@ -46,7 +46,9 @@ struct DevSystem {
     const int* e_rp;
     const int* e_ci;
     const double2* e_val;
-    const double* f_diag;      // [12][d] diagonal feature operators (learned form)
+    const double* f_diag;      // [12 + n_c][d]: rows 0..11 diagonal feature operators (learned form),
+                               // rows 12 + n: diagonal of C_n^dag C_n when c_isdiag
+    int c_isdiag;              // every C_n has at most one entry per row, so C_n^dag C_n is diagonal
     const double2* psi0;       // [d]
     const double* tlist;       // [n_t]
     double t0, tend;
@@ -75,7 +77,7 @@ struct RunArgs {
     const float* mlp;          // [kNTotal] weights (BF16-rounded values), biases, mean, scale
     const unsigned short* mlpf;  // [kMlpFrag] BF16 weight fragments for the matrix-core evaluation
     long long* fail;           // smallest failing global trajectory index (LLONG_MAX: none)
-    unsigned long long* counters;  // [4]: passes, rhs column-evaluations, cycles, unused
+    unsigned long long* counters;  // [4]: product passes (sum over teams), unused, most passes of one team, unused
     long long max_cycles;      // failsafe bound on block cycles
     int tile_cols;             // requested columns per block (0: as many as the waves allow)
     int persistent;            // refill free slots from the queue

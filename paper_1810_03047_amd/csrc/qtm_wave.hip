@@ -21,10 +21,25 @@
 
 namespace qtm {
 
-__device__ __forceinline__ double csum(double x) {
-    x += __shfl_xor(x, 16);
-    x += __shfl_xor(x, 32);
-    return x;
+// Sum over the four lanes of a column (lane & 15) with the gfx950 VALU lane swaps:
+// permlane32_swap pairs lanes l and l ^ 32, permlane16_swap then lanes l and l ^ 16.
+// Each addition is commutative, so every lane of a column ends with identical bits.
+__device__ __forceinline__ double swap_add32(double v) {
+    auto a = __builtin_amdgcn_permlane32_swap(__double2loint(v), __double2loint(v), false, false);
+    auto b = __builtin_amdgcn_permlane32_swap(__double2hiint(v), __double2hiint(v), false, false);
+    return __hiloint2double(b[0], a[0]) + __hiloint2double(b[1], a[1]);
+}
+__device__ __forceinline__ double swap_add16(double v) {
+    auto a = __builtin_amdgcn_permlane16_swap(__double2loint(v), __double2loint(v), false, false);
+    auto b = __builtin_amdgcn_permlane16_swap(__double2hiint(v), __double2hiint(v), false, false);
+    return __hiloint2double(b[0], a[0]) + __hiloint2double(b[1], a[1]);
+}
+__device__ __forceinline__ double csum(double x) { return swap_add16(swap_add32(x)); }
+__device__ __forceinline__ float csumf(float v) {
+    auto a = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    v = __uint_as_float(a[0]) + __uint_as_float(a[1]);
+    auto b = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return __uint_as_float(b[0]) + __uint_as_float(b[1]);
 }
 __device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ULL; }
 __device__ __forceinline__ void wave_sync() {
@@ -34,6 +49,15 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 constexpr int kXV = 8;       // values per column in one team reduction
+
+// [theta^i] of the dense-output weights c_a(theta) = (1, th, th(1-th), th^2(1-th), th^2(1-th)^2)
+__device__ __forceinline__ constexpr double dense_coef(int a, int i) {
+    return a == 0 ? (i == 0 ? 1.0 : 0.0)
+         : a == 1 ? (i == 1 ? 1.0 : 0.0)
+         : a == 2 ? (i == 1 ? 1.0 : i == 2 ? -1.0 : 0.0)
+         : a == 3 ? (i == 2 ? 1.0 : i == 3 ? -1.0 : 0.0)
+         : (i == 2 ? 1.0 : i == 3 ? -2.0 : i == 4 ? 1.0 : 0.0);
+}
 
 template <int T, int NWT, int PREC>
 struct Team {
@@ -50,11 +74,12 @@ struct Team {
     unsigned long long* Ib;  // LDS: trajectory hand-out [16]
     int* Fb;                 // LDS: team flags [4]
     const double2* Od;       // LDS copy of the diagonal observables [n_e][d] (when od_lds)
+    const float* Ft;         // LDS: FP32 feature table [d][16] (rows 12, 13: C_n^dag C_n when diagonal)
     int od_lds;
     int lane, lg, c16, wv, RT, d, dp, q0;
 
     // per-lane trajectory state (identical on every lane of a column, on every wave)
-    double t, h, h0, d1, r, u, tseg, tb, fac, th, oth, tnext;
+    double t, h, h0, d1, r, u, tseg, tb, fac, th, oth, tnext, tnext2;   // output times k, k + 1
     long long traj;
     int state, action, seg, kk, nacc, nrej, njump, natt, last, rejected, omode, ch, seg_rec, first_acc;
     bool exhausted;
@@ -81,7 +106,11 @@ struct Team {
     // 2 tt and 2 tt + 1 are accumulator slots (0, 1) and (2, 3) of tile tt.
     // Components at or past d (padding, or tiles past RT) are invalid.
     static constexpr int cst(int e) { return PREC == 0 ? 8 * (e >> 1) + 4 * (e & 1) : 8 * (e >> 1) + (e & 1); }
-    QTM_DI int comp(int e) const { int q = q0 + cst(e); return q < d ? q : -1; }
+    // q0 passed through an empty asm statement: addresses built from it are recomputed
+    // where they are used (two VALU ops) instead of being hoisted out of the main loop,
+    // where they would live for the whole kernel and end up in scratch
+    QTM_DI int qbase() const { int x = q0; asm volatile("" : "+v"(x)); return x; }
+    QTM_DI int comp(int e) const { int q = qbase() + cst(e); return q < d ? q : -1; }
 
     // team-wide per-column sums of NV values (NV <= kXV), identical on every lane
     template <int NV> QTM_DI void tsum(double (&p)[NV]) {
@@ -99,6 +128,24 @@ struct Team {
 #pragma unroll
             for (int g = 0; g < NWT; ++g) s += Xb[(g * 16 + c16) * kXV + v];
             p[v] = s;
+        }
+        __syncthreads();
+    }
+    template <int NV> QTM_DI void tsumf(float (&p)[NV]) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) p[v] = csumf(p[v]);
+        if (NWT == 1) return;
+        if (lg == 0) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) Xb[(wv * 16 + c16) * kXV + v] = p[v];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            double sv = 0.0;
+#pragma unroll
+            for (int g = 0; g < NWT; ++g) sv += Xb[(g * 16 + c16) * kXV + v];
+            p[v] = (float)sv;
         }
         __syncthreads();
     }
@@ -211,37 +258,57 @@ struct Team {
     // <u|O_o|u>/<u|u> for every lane with omode != 0 (one team reduction per observable)
     QTM_DI void output_round(bool on) {
         double2 uu[NE];
+        int qi[NE];
         double nn = 0.0;
+        const int qb = qbase();
 #pragma unroll
         for (int e = 0; e < NE; ++e) {
-            int q = comp(e);
-            uu[e] = (on && q >= 0) ? vec_mode(e) : make_double2(0.0, 0.0);
+            const int q = qb + cst(e);
+            uu[e] = (on && q < d) ? vec_mode(e) : make_double2(0.0, 0.0);
+            qi[e] = q < d ? q : 0;
             nn += cabs2(uu[e]);
         }
-        nn = tsum1(nn);
         if (S.any_csr_e) stage_vec(uu);
-        for (int o = 0; o < S.n_e; ++o) {
-            double p[2] = {0.0, 0.0};
-            const bool diag = S.e_fmt[o] == 2;
-            const double2* dv = od_lds ? Od + (size_t)o * d : S.e_val + S.e_doff[o];
-            const int* rp = S.e_rp + (size_t)o * (S.d + 1);
+        // up to three observables and the norm per team reduction
+        for (int o0 = 0; o0 < S.n_e; o0 += 3) {
+            double p[7];
 #pragma unroll
-            for (int e = 0; e < NE; ++e) {
-                int q = comp(e);
-                if (q < 0 || !on) continue;
-                if (diag) {
-                    double a2 = cabs2(uu[e]);
-                    double2 v = dv[q];
-                    p[0] += v.x * a2;
-                    p[1] += v.y * a2;
+            for (int v = 0; v < 6; ++v) p[v] = 0.0;
+            p[6] = o0 == 0 ? nn : 0.0;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const int o = o0 + j;
+                if (o >= S.n_e) break;
+                if (S.e_fmt[o] == 2) {
+                    const double2* dv = od_lds ? Od + (size_t)o * d : S.e_val + S.e_doff[o];
+#pragma unroll
+                    for (int e = 0; e < NE; ++e) {
+                        const double a2 = cabs2(uu[e]);
+                        const double2 v = dv[qi[e]];
+                        p[2 * j] = fma(v.x, a2, p[2 * j]);
+                        p[2 * j + 1] = fma(v.y, a2, p[2 * j + 1]);
+                    }
                 } else {
-                    double2 Ou = csr_row(rp, S.e_ci, S.e_val, q);
-                    p[0] += uu[e].x * Ou.x + uu[e].y * Ou.y;     // Re conj(u) O u
-                    p[1] += uu[e].x * Ou.y - uu[e].y * Ou.x;     // Im conj(u) O u
+                    const int* rp = S.e_rp + (size_t)o * (S.d + 1);
+#pragma unroll
+                    for (int e = 0; e < NE; ++e) {
+                        int q = comp(e);
+                        if (q < 0 || !on) continue;
+                        double2 Ou = csr_row(rp, S.e_ci, S.e_val, q);
+                        p[2 * j] += uu[e].x * Ou.x + uu[e].y * Ou.y;     // Re conj(u) O u
+                        p[2 * j + 1] += uu[e].x * Ou.y - uu[e].y * Ou.x; // Im conj(u) O u
+                    }
                 }
             }
-            tsum<2>(p);
-            if (on && lg == 0 && wv == 0) S.X[((size_t)traj * S.n_e + o) * S.n_t + kk] = make_double2(p[0] / nn, p[1] / nn);
+            tsum<7>(p);
+            if (o0 == 0) nn = p[6];
+            if (on && lg == 0 && wv == 0) {
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    const int o = o0 + j;
+                    if (o < S.n_e) S.X[((size_t)traj * S.n_e + o) * S.n_t + kk] = make_double2(p[2 * j] / nn, p[2 * j + 1] / nn);
+                }
+            }
         }
     }
 
@@ -272,7 +339,9 @@ struct Team {
             output_round(on);
             if (on) {
                 kk++;
-                tnext = kk < S.n_t ? S.tlist[kk] : 0.0;
+                // the time after next is requested now and first needed a round later
+                tnext = tnext2;
+                tnext2 = kk + 1 < S.n_t ? S.tlist[kk + 1] : 0.0;
             }
         }
         omode = 0;
@@ -293,7 +362,7 @@ struct Team {
     QTM_DI void run() {
         const double tend = S.tend;
         state = ST_EMPTY; traj = -1; action = ACT_NONE; omode = 0; exhausted = false;
-        t = h = h0 = d1 = r = u = tseg = tb = fac = th = oth = tnext = 0.0;
+        t = h = h0 = d1 = r = u = tseg = tb = fac = th = oth = tnext = tnext2 = 0.0;
         seg = kk = nacc = nrej = njump = natt = last = rejected = ch = seg_rec = first_acc = 0;
 #pragma unroll
         for (int e = 0; e < NE; ++e) {
@@ -320,6 +389,7 @@ struct Team {
                     t = S.t0; seg = 0; kk = 0; nacc = nrej = njump = natt = 0;
                     rejected = 0; seg_rec = 0;
                     tnext = S.tlist[0];
+                    tnext2 = S.n_t > 1 ? S.tlist[1] : 0.0;
                     state = ST_NEW;
                 } else {
                     exhausted = true;
@@ -398,43 +468,67 @@ struct Team {
     // 16 segment-start features; the learned form turns them into the first step
     QTM_DI void features() {
         const bool on = state == ST_NEEDK1;
-        if (S.n_c > 0) {
+        const bool cd = S.c_isdiag != 0;
+        if (!cd && S.n_c > 0) {
             double2 v[NE];
 #pragma unroll
             for (int e = 0; e < NE; ++e) v[e] = on ? y[e] : make_double2(0.0, 0.0);
             stage_vec(v);
         }
+        // populations |y_q|^2 (zero off the trajectory's valid components) against the
+        // FP32 table [q][16] (rows: 12 feature populations, <C_n^dag C_n> for n < 2 when
+        // diagonal), four 16-byte LDS reads per component, FP32 sums; norm in FP64
         float f[kNF];
         double nn = 0.0;
+        float acc[16];
 #pragma unroll
-        for (int e = 0; e < NE; ++e)
-            if (on && comp(e) >= 0) nn += cabs2(y[e]);
-        nn = tsum1(nn);
-        for (int fi = 0; fi < 12; ++fi) {
-            double acc = 0.0;
-            if (fi < S.n_f) {
-                const double* fd = S.f_diag + (size_t)fi * S.d;
+        for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+        const int qb = qbase();
 #pragma unroll
-                for (int e = 0; e < NE; ++e) {
-                    int q = comp(e);
-                    if (on && q >= 0) acc += fd[q] * cabs2(y[e]);
-                }
-                acc = tsum1(acc);
+        for (int e = 0; e < NE; ++e) {
+            const int q = qb + cst(e);
+            const bool ok = on && q < d;
+            const double a2 = ok ? cabs2(y[e]) : 0.0;
+            nn += a2;
+            const float af = (float)a2;
+            const float4* row = (const float4*)(Ft + (q < d ? q : 0) * 16);
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const float4 v = row[g];
+                acc[4 * g + 0] = fmaf(v.x, af, acc[4 * g + 0]);
+                acc[4 * g + 1] = fmaf(v.y, af, acc[4 * g + 1]);
+                acc[4 * g + 2] = fmaf(v.z, af, acc[4 * g + 2]);
+                acc[4 * g + 3] = fmaf(v.w, af, acc[4 * g + 3]);
             }
-            f[fi] = (float)(acc / nn);
         }
-        for (int n = 0; n < 2; ++n) {
-            double acc = 0.0;
-            if (n < S.n_c) {
-                const int* rp = S.c_rp + (size_t)n * (S.d + 1);
+        nn = tsum1(nn);
+        {
+            float h0f[8], h1f[8];
 #pragma unroll
-                for (int e = 0; e < NE; ++e) {
-                    int q = comp(e);
-                    if (on && q >= 0) acc += cabs2(csr_row(rp, S.c_ci, S.c_val, q));
+            for (int r = 0; r < 7; ++r) { h0f[r] = acc[r]; h1f[r] = acc[7 + r]; }
+            h0f[7] = h1f[7] = 0.f;
+            tsumf<8>(h0f);
+            tsumf<8>(h1f);
+            const float inv = (float)(1.0 / nn);
+#pragma unroll
+            for (int r = 0; r < 7; ++r) { f[r] = h0f[r] * inv; f[7 + r] = h1f[r] * inv; }
+        }
+        double pv0 = nn;
+        if (!cd) {
+            // general collapse operators: ||C_n y||^2 from the staged state
+            for (int n = 0; n < 2; ++n) {
+                double acc = 0.0;
+                if (n < S.n_c) {
+                    const int* rp = S.c_rp + (size_t)n * (S.d + 1);
+#pragma unroll
+                    for (int e = 0; e < NE; ++e) {
+                        int q = comp(e);
+                        if (on && q >= 0) acc += cabs2(csr_row(rp, S.c_ci, S.c_val, q));
+                    }
+                    acc = tsum1(acc);
                 }
-                acc = tsum1(acc);
+                f[12 + n] = (float)(acc / pv0);
             }
-            f[12 + n] = (float)(acc / nn);
         }
         if (!on) {
 #pragma unroll
@@ -475,46 +569,72 @@ struct Team {
         const float* sd = mu + kNF;
         const uint2* F = (const uint2*)A.mlpf;          // 4 BF16 values per lane and group
         auto bf = [](unsigned int w, int hi) { return __uint_as_float(hi ? (w & 0xFFFF0000u) : (w << 16)); };
+        // every operand of the three layers is requested at once (one memory latency per
+        // call); the biases b1, b2 sit at multiples of 4 floats from the 256-byte aligned start
+        uint2 w1[4], w2[16], w3[4];
+        float4 c1[4], c2[4];
+#pragma unroll
+        for (int g = 0; g < 4; ++g) w1[g] = F[(size_t)g * 64 + lane];
+#pragma unroll
+        for (int g = 0; g < 16; ++g) w2[g] = F[(size_t)(4 + g) * 64 + lane];
+#pragma unroll
+        for (int g = 0; g < 4; ++g) w3[g] = F[(size_t)(20 + g) * 64 + lane];
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) {
+            c1[rt] = *(const float4*)(b1 + 16 * rt + 4 * lg);
+            c2[rt] = *(const float4*)(b2 + 16 * rt + 4 * lg);
+        }
+        // mean and scale start at an odd offset: plain scalar loads
+        float m4[4], s4[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) { m4[j] = mu[4 * lg + j]; s4[j] = sd[4 * lg + j]; }
+        const float ob = b3[0];
         float x[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const float v = lg == 0 ? f[j] : lg == 1 ? f[4 + j] : lg == 2 ? f[8 + j] : f[12 + j];
-            x[j] = (v - mu[4 * lg + j]) / sd[4 * lg + j];
+            x[j] = (v - m4[j]) / s4[j];
         }
         float h1[4][4], h2[4][4];
+        f4 z1[4], z2[4];
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) z1[rt] = 0;
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt)
+                z1[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(bf(kb < 2 ? w1[rt].x : w1[rt].y, kb & 1), x[kb], z1[rt], 0, 0, 0);
 #pragma unroll
         for (int rt = 0; rt < 4; ++rt) {
-            f4 z = 0;
-            const uint2 wq = F[(size_t)rt * 64 + lane];
-#pragma unroll
-            for (int kb = 0; kb < 4; ++kb)
-                z = __builtin_amdgcn_mfma_f32_16x16x4f32(bf(kb < 2 ? wq.x : wq.y, kb & 1), x[kb], z, 0, 0, 0);
-#pragma unroll
-            for (int i = 0; i < 4; ++i) h1[rt][i] = gelu_f(z[i] + b1[16 * rt + 4 * lg + i]);
+            h1[rt][0] = gelu_f(z1[rt][0] + c1[rt].x); h1[rt][1] = gelu_f(z1[rt][1] + c1[rt].y);
+            h1[rt][2] = gelu_f(z1[rt][2] + c1[rt].z); h1[rt][3] = gelu_f(z1[rt][3] + c1[rt].w);
+            z2[rt] = 0;
         }
+        // four independent accumulation chains (output tiles) interleaved
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int rt = 0; rt < 4; ++rt) {
+                    const uint2 wq = w2[4 * rt + s2];
+                    z2[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(bf(i < 2 ? wq.x : wq.y, i & 1), h1[s2][i], z2[rt], 0, 0, 0);
+                }
 #pragma unroll
         for (int rt = 0; rt < 4; ++rt) {
-            f4 z = 0;
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const uint2 wq = F[(size_t)(4 + 4 * rt + s) * 64 + lane];
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    z = __builtin_amdgcn_mfma_f32_16x16x4f32(bf(i < 2 ? wq.x : wq.y, i & 1), h1[s][i], z, 0, 0, 0);
-            }
-#pragma unroll
-            for (int i = 0; i < 4; ++i) h2[rt][i] = gelu_f(z[i] + b2[16 * rt + 4 * lg + i]);
+            h2[rt][0] = gelu_f(z2[rt][0] + c2[rt].x); h2[rt][1] = gelu_f(z2[rt][1] + c2[rt].y);
+            h2[rt][2] = gelu_f(z2[rt][2] + c2[rt].z); h2[rt][3] = gelu_f(z2[rt][3] + c2[rt].w);
         }
         f4 o = 0;
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const uint2 wq = F[(size_t)(20 + s) * 64 + lane];
+        for (int s2 = 0; s2 < 4; ++s2) {
+            const uint2 wq = w3[s2];
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-                o = __builtin_amdgcn_mfma_f32_16x16x4f32(bf(i < 2 ? wq.x : wq.y, i & 1), h2[s][i], o, 0, 0, 0);
+                o = __builtin_amdgcn_mfma_f32_16x16x4f32(bf(i < 2 ? wq.x : wq.y, i & 1), h2[s2][i], o, 0, 0, 0);
         }
         // output 0 is row 0: slot 0 of lane group 0
-        return __shfl(o[0] + b3[0], c16);
+        return __shfl(o[0] + ob, c16);
     }
 
     // stage s (0-based): w = y + sum_j c_j k_j, k_s = M w
@@ -655,11 +775,9 @@ struct Team {
     // v = {y, D, B, R4, R5}: u = sum_p c_p v_p, c = (1, th, th(1-th), th^2(1-th), th^2(1-th)^2)
     QTM_DI void jump_time() {
         const bool on = action == ACT_JUMP;
-        double g0[8], g1[7];
+        double g[15];
 #pragma unroll
-        for (int n = 0; n < 8; ++n) g0[n] = 0.0;
-#pragma unroll
-        for (int n = 0; n < 7; ++n) g1[n] = 0.0;
+        for (int n = 0; n < 15; ++n) g[n] = 0.0;
         if (on) {
 #pragma unroll
             for (int e = 0; e < NE; ++e) {
@@ -676,29 +794,49 @@ struct Team {
                 for (int a = 0; a < 5; ++a)
 #pragma unroll
                     for (int b = a; b < 5; ++b) {
-                        double gv = v[a].x * v[b].x + v[a].y * v[b].y;
-                        if (n < 8) g0[n] += gv; else g1[n - 8] += gv;
+                        g[n] += v[a].x * v[b].x + v[a].y * v[b].y;
                         ++n;
                     }
             }
         }
-        tsum<8>(g0);
-        tsum<7>(g1);
+        {
+            // two team reductions of at most kXV values
+            double g0[8], g1[7];
+#pragma unroll
+            for (int n = 0; n < 8; ++n) g0[n] = g[n];
+#pragma unroll
+            for (int n = 0; n < 7; ++n) g1[n] = g[8 + n];
+            tsum<8>(g0);
+            tsum<7>(g1);
+#pragma unroll
+            for (int n = 0; n < 8; ++n) g[n] = g0[n];
+#pragma unroll
+            for (int n = 0; n < 7; ++n) g[8 + n] = g1[n];
+        }
         if (on) {
+            // ||u(theta)||^2 as a degree-8 polynomial: P_k = sum_{a<=b} w_ab G_ab [theta^k] c_a c_b
+            double P[9];
+#pragma unroll
+            for (int k2 = 0; k2 < 9; ++k2) P[k2] = 0.0;
+            int n = 0;
+#pragma unroll
+            for (int a = 0; a < 5; ++a)
+#pragma unroll
+                for (int b = a; b < 5; ++b) {
+#pragma unroll
+                    for (int i = 0; i < 5; ++i)
+#pragma unroll
+                        for (int j = 0; j < 5; ++j) {
+                            const double cij = dense_coef(a, i) * dense_coef(b, j);
+                            if (cij != 0.0) P[i + j] = fma((a == b ? 1.0 : 2.0) * cij, g[n], P[i + j]);
+                        }
+                    ++n;
+                }
             auto f = [&](double x) {
-                double t1 = 1.0 - x;
-                double cc[5] = {1.0, x, x * t1, x * x * t1, x * x * t1 * t1};
-                double s = 0.0;
-                int n = 0;
+                double v = P[8];
 #pragma unroll
-                for (int a = 0; a < 5; ++a)
-#pragma unroll
-                    for (int b = a; b < 5; ++b) {
-                        double g = n < 8 ? g0[n] : g1[n - 8];
-                        s += (a == b ? 1.0 : 2.0) * cc[a] * cc[b] * g;
-                        ++n;
-                    }
-                return s - r;
+                for (int k2 = 7; k2 >= 0; --k2) v = fma(v, x, P[k2]);
+                return v - r;
             };
             double lo = 0.0, hi = 1.0;
             for (int m = 1; m <= 32; ++m) {
@@ -716,12 +854,21 @@ struct Team {
 
     // ||C_n psi*||^2 for this lane's trajectory (psi* staged); uniform call
     QTM_DI double chan_prob(int n, bool on) {
-        const int* rp = S.c_rp + (size_t)n * (S.d + 1);
         double acc = 0.0;
+        if (S.c_isdiag) {
+            const double* g = S.f_diag + (size_t)(12 + n) * S.d;
 #pragma unroll
-        for (int e = 0; e < NE; ++e) {
-            int q = comp(e);
-            if (on && q >= 0) acc += cabs2(csr_row(rp, S.c_ci, S.c_val, q));
+            for (int e = 0; e < NE; ++e) {
+                const int q = comp(e);
+                if (on && q >= 0) acc += g[q] * cabs2(St[q * 16 + c16]);
+            }
+        } else {
+            const int* rp = S.c_rp + (size_t)n * (S.d + 1);
+#pragma unroll
+            for (int e = 0; e < NE; ++e) {
+                const int q = comp(e);
+                if (on && q >= 0) acc += cabs2(csr_row(rp, S.c_ci, S.c_val, q));
+            }
         }
         return tsum1(acc);
     }
@@ -792,9 +939,9 @@ struct Team {
 };
 
 // LDS of a block: [A-fragments of M][per team: operand tile, team exchange, hand-out, flags]
-// [diagonal observables].  Blocks of single-wave teams hold TPB teams that share M
-// and never meet at a barrier after the set-up.
-struct TeamLds { size_t m, team, w, x, ib, fb, od, total; };
+// [diagonal observables][FP32 feature table].  Blocks of single-wave teams hold TPB teams
+// that share M and never meet at a barrier after the set-up.
+struct TeamLds { size_t m, team, w, x, ib, fb, od, ft, total; };
 static __host__ __device__ TeamLds team_lds(int dp, int d, int n_e, int prec, int nwt, int tpb, int od_lds) {
     TeamLds L;
     size_t es = prec == 0 ? 8 : 4;
@@ -805,7 +952,8 @@ static __host__ __device__ TeamLds team_lds(int dp, int d, int n_e, int prec, in
     L.fb = L.ib + 16 * sizeof(unsigned long long);
     L.team = (L.fb + 16 + 15) & ~(size_t)15;                                // bytes per team
     L.od = L.w + (size_t)tpb * L.team;
-    L.total = L.od + (od_lds ? (size_t)n_e * d * sizeof(double2) : 0);
+    L.ft = L.od + (od_lds ? (size_t)n_e * d * sizeof(double2) : 0);
+    L.total = L.ft + (size_t)16 * d * sizeof(float);                      // FP32 feature table [d][16]
     return L;
 }
 
@@ -824,6 +972,14 @@ __global__ void __launch_bounds__(NWT == 1 ? 256 : 64 * NWT) traj_team_kernel(Ru
     if (od_lds)
         for (int o = 0; o < S.n_e; ++o)
             for (int i = threadIdx.x; i < S.d; i += blockDim.x) Odl[(size_t)o * S.d + i] = S.e_val[S.e_doff[o] + i];
+    // segment-start features: rows 0..11 of the diagonal table and, when C^dag C is
+    // diagonal, rows 12..13 (first two channels), in FP32
+    float* Ftl = (float*)(base + L.ft);
+    for (int i = threadIdx.x; i < 16 * S.d; i += blockDim.x) {
+        const int q = i >> 4, row = i & 15;
+        const bool have = row < 12 || (row < 14 && S.c_isdiag && row - 12 < S.n_c);
+        Ftl[i] = have ? (float)S.f_diag[(size_t)row * S.d + q] : 0.f;
+    }
     __syncthreads();
     const int team = (threadIdx.x >> 6) / NWT;
     char* tb = base + L.w + (size_t)team * L.team;
@@ -836,6 +992,7 @@ __global__ void __launch_bounds__(NWT == 1 ? 256 : 64 * NWT) traj_team_kernel(Ru
     W.Fb = (int*)(tb + L.fb);
     W.Od = Odl;
     W.od_lds = od_lds;
+    W.Ft = Ftl;
     W.lane = threadIdx.x & 63;
     W.wv = (threadIdx.x >> 6) % NWT;
     W.lg = W.lane >> 4;
@@ -845,7 +1002,10 @@ __global__ void __launch_bounds__(NWT == 1 ? 256 : 64 * NWT) traj_team_kernel(Ru
     W.RT = 2 * S.dp / 16;
     W.q0 = 8 * T * W.wv + (PREC == 0 ? W.lg : 2 * W.lg);
     W.run();
-    if ((threadIdx.x & 63) == 0 && W.wv == 0) atomicAdd(&a.counters[0], W.passes);
+    if ((threadIdx.x & 63) == 0 && W.wv == 0) {
+        atomicAdd(&a.counters[0], W.passes);
+        atomicMax(&a.counters[2], W.passes);
+    }
 }
 
 #ifndef QTM_WAVE_INSTANCES
@@ -858,13 +1018,13 @@ template <int T, int NWT, int PREC> const void* team_fn_inst();
 static const int kShapes[9][3][2] = {
     {{0, 0}, {0, 0}, {0, 0}},
     {{1, 1}, {0, 0}, {0, 0}},
-    {{1, 2}, {2, 1}, {0, 0}},
-    {{1, 3}, {2, 2}, {3, 1}},
-    {{1, 4}, {2, 2}, {4, 1}},
-    {{1, 5}, {3, 2}, {5, 1}},
-    {{1, 6}, {2, 3}, {3, 2}},
-    {{1, 7}, {4, 2}, {0, 0}},
-    {{1, 8}, {2, 4}, {4, 2}},
+    {{2, 1}, {1, 2}, {0, 0}},
+    {{3, 1}, {2, 2}, {1, 3}},
+    {{4, 1}, {2, 2}, {1, 4}},
+    {{5, 1}, {3, 2}, {1, 5}},
+    {{3, 2}, {2, 3}, {1, 6}},
+    {{4, 2}, {1, 7}, {0, 0}},
+    {{2, 4}, {4, 2}, {1, 8}},
 };
 
 // waves_per_team: 0 = default shape, else the listed shape with that many waves
@@ -903,20 +1063,43 @@ int wave_supported(int d) {
     return team_shape(rt, 0, &T, &nwt) == 0;
 }
 
+// LDS of a team-kernel block for one shape; tpb reduced until it fits (0 if it never does)
+static size_t team_block_lds(int dp, const DevSystem& s0, int prec, int nwt, int od_lds, int* tpb) {
+    *tpb = nwt == 1 ? 4 : 1;
+    TeamLds L = team_lds(dp, s0.d, s0.n_e, prec, nwt, *tpb, od_lds);
+    while (*tpb > 1 && L.total > 160 * 1024) L = team_lds(dp, s0.d, s0.n_e, prec, nwt, --*tpb, od_lds);
+    return L.total > 160 * 1024 ? 0 : L.total;
+}
+
 int launch_wave(const RunArgs& a, const DevSystem& s0, int prec, int waves_per_team, hipStream_t st, LaunchInfo* info) {
     int dp = s0.dp, rt = 2 * dp / 16, T, nwt;
     if (team_shape(rt, waves_per_team, &T, &nwt)) return -1;
-    if (nwt == 1 && T != rt) return -1;          // a single-wave team holds every source tile
-    const void* fn = team_fn(T, nwt, prec);
-    if (!fn) return -1;
     // diagonal observables are copied to LDS when every observable is diagonal
     int od_lds = 1;
     for (int o = 0; o < s0.n_e; ++o) if (s0.e_fmt[o] != 2) od_lds = 0;
-    // single-wave teams: up to 4 per block, sharing the operator in LDS
-    int tpb = nwt == 1 ? 4 : 1;
-    TeamLds L = team_lds(dp, s0.d, s0.n_e, prec, nwt, tpb, od_lds);
-    while (tpb > 1 && L.total > 160 * 1024) L = team_lds(dp, s0.d, s0.n_e, prec, nwt, --tpb, od_lds);
-    if (L.total > 160 * 1024) return -1;
+    // single-wave teams: up to 4 per block, sharing the operator in LDS; a shape whose
+    // block does not fit the 160 KB of LDS gives way to the next shape of the same tile count
+    int tpb = 1;
+    size_t lds = team_block_lds(dp, s0, prec, nwt, od_lds, &tpb);
+    for (int i = 0; i < 3 && lds == 0 && waves_per_team == 0; ++i) {
+        T = kShapes[rt][i][0]; nwt = kShapes[rt][i][1];
+        if (T) lds = team_block_lds(dp, s0, prec, nwt, od_lds, &tpb);
+    }
+    if (lds == 0 && od_lds) {                    // observables stay in global memory
+        od_lds = 0;
+        team_shape(rt, waves_per_team, &T, &nwt);
+        lds = team_block_lds(dp, s0, prec, nwt, od_lds, &tpb);
+        for (int i = 0; i < 3 && lds == 0 && waves_per_team == 0; ++i) {
+            T = kShapes[rt][i][0]; nwt = kShapes[rt][i][1];
+            if (T) lds = team_block_lds(dp, s0, prec, nwt, od_lds, &tpb);
+        }
+    }
+    if (lds == 0) return -2;
+    if (nwt == 1 && T != rt) return -1;          // a single-wave team holds every source tile
+    const void* fn = team_fn(T, nwt, prec);
+    if (!fn) return -1;
+    TeamLds L;
+    L.total = lds;
     if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.total) != hipSuccess) return -3;
     int dev = 0, ncu = 0, nb = 1;
     const int threads = nwt * tpb * 64;

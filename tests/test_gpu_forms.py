@@ -114,6 +114,22 @@ def test_team_shapes_agree(waves):
     _exact(ctx, r, n)
 
 
+@pytest.mark.parametrize("d", [16, 24, 32, 48, 56, 64])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_team_dimensions(d, prec):
+    """Default team shape for every tile count (d = 16 .. 64): FP64 exact, FP32 close."""
+    s = w.jaynes_cummings(N=d // 2, t_end=4.0, n_t=41)
+    n = 32
+    ctx = _gpu(s, n, seed=d, precision=prec, form=qtm.FORM_BATCHED)
+    r = oracle.run(s, n, seed=d, jcap=32)
+    if prec == 0:
+        _exact(ctx, r, n)
+    else:
+        _, _, jn = _jumps(ctx, n)
+        assert np.mean(jn == r["jump_counts"]) > 0.9
+        assert np.max(np.abs(ctx.traj_expect() - r["X"])) < 1e-3
+
+
 # ------------------------------------------------------------------ batch of mixed dimension
 def test_batch_mixed_dimension_fp64_exact():
     rng = np.random.Generator(np.random.Philox(key=3))
@@ -247,3 +263,40 @@ def test_segment_records_for_training():
             if r["segs"][i, z, 18] == 0:
                 assert abs(seg[i, z, 16] - r["segs"][i, z, 16]) <= 1e-5 * (1 + abs(r["segs"][i, z, 16]))
             assert abs(seg[i, z, 17] - r["segs"][i, z, 17]) <= 1e-5 * abs(r["segs"][i, z, 17])
+
+
+def test_trained_proposal_gains_over_starting_step_rule():
+    """The proposal trained on the device from segment records of the plain solver
+    takes fewer attempted steps per trajectory and a shorter critical path (most
+    product passes of one 16-trajectory team) than the starting-step rule, on the
+    same trajectories.  Measured, not pinned: the size of the gain is reported."""
+    s = w.jaynes_cummings(t_end=20.0, n_t=201)
+    f_ops = _jcm_feature_ops(20)
+    gen = qtm.create_system(s, qtm.Opts(seg_cap=16, form=qtm.FORM_BATCHED))
+    p0 = np.zeros(qtm.MLP_NTOTAL, dtype=np.float32)
+    p0[-16:] = 1.0
+    gen.set_proposal(p0, f_ops)
+    gen.run_range(0, 20000, 11)
+    seg = gen.segments().reshape(-1, qtm.SEG_REC)
+    seg = seg[(seg[:, 19] > 0) & (seg[:, 17] > 0)]
+    tau = np.where(seg[:, 18] > 0, 1.0, seg[:, 16])
+    F = seg[:, :16].astype(np.float32)
+    T = np.stack([np.log(seg[:, 17]), np.log(np.maximum(tau, 1e-12)), seg[:, 18]], 1).astype(np.float32)
+    losses = gen.train_proposal(F, T, epochs=8, batch=4096, lr=2e-3, seed=0)
+    prop = gen.get_proposal()
+    res = {}
+    for name, form in (("rule", qtm.FORM_BATCHED), ("learned", qtm.FORM_BATCHED | qtm.FORM_LEARNED)):
+        ctx = qtm.create_system(s, qtm.Opts(form=form))
+        if form & qtm.FORM_LEARNED:
+            ctx.set_proposal(prop, f_ops)
+        ctx.run(4000, 3)
+        st = ctx.stats()
+        res[name] = (st["accepted"] + st["rejected"], st["max_team_passes"], st["passes"])
+        ctx.destroy()
+    print(f"training loss {losses[0]:.4f} -> {losses[-1]:.4f} on {len(F)} samples; "
+          f"attempted steps rule {res['rule'][0]} learned {res['learned'][0]}; "
+          f"critical path rule {res['rule'][1]} learned {res['learned'][1]} passes; "
+          f"total passes rule {res['rule'][2]} learned {res['learned'][2]}")
+    assert losses[-1] < losses[0]
+    assert res["learned"][0] < res["rule"][0]
+    assert res["learned"][2] < res["rule"][2]
