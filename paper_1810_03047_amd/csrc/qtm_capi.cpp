@@ -237,6 +237,11 @@ struct qtm_ctx {
     long long last_begin = 0, last_count = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     int ncu = 0;
+    bool batch = false;                // created by qtm_create_batch
+    // per-system launches of a batch fan out over these streams (default priority)
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> side_ev;
+    hipEvent_t fork = nullptr;
 };
 
 namespace {
@@ -275,7 +280,7 @@ int ensure_buf(DevBuf& b, size_t bytes) {
     return QTM_OK;
 }
 
-int setup_system(SysHost& S, const qtm_system& in, int idx, const qtm_opts& o, bool allow_sparse) {
+int setup_system(SysHost& S, const qtm_system& in, int idx, const qtm_opts& o, bool want_ell) {
     const qtm_op* H = in.H;
     if (!H) return fail(QTM_E_INVAL, "system %d: null H", idx);
     const int d = H->dim;
@@ -302,7 +307,6 @@ int setup_system(SysHost& S, const qtm_system& in, int idx, const qtm_opts& o, b
     }
     // kernel choice: CSR H -> sliced-ELL SpMM; dense H -> MFMA team kernel (d <= 64),
     // MFMA block kernel (d <= 128), or the SpMM kernel on full rows (d <= 2048)
-    (void)allow_sparse;
     S.sparse = H->fmt == QTM_FMT_CSR || d > 128;
     S.team = !S.sparse && qtm::wave_supported(d);
     if (d > 2048) return fail(QTM_E_INVAL, "system %d: dimension %d above the supported 2048", idx, d);
@@ -325,9 +329,12 @@ int setup_system(SysHost& S, const qtm_system& in, int idx, const qtm_opts& o, b
             if ((rc = upload(S, &D.Mfrag, build_frag<double>(M, dp, 0)))) return rc;
             if ((rc = upload(S, &D.Mfrag32, build_frag<float>(M, dp, 1)))) return rc;
         }
-
     } else {
         D.dp = d;
+    }
+    // sliced ELL: for the SpMM kernel, and for every system of a batch (the single
+    // launch over all systems runs on it)
+    if (S.sparse || want_ell) {
         int nsl = (d + 63) / 64;
         std::vector<int> off(nsl + 1, 0), wd(nsl, 0);
         for (int s = 0; s < nsl; ++s) {
@@ -561,7 +568,7 @@ int qtm_tile_candidates(int32_t d, int32_t* waves, int32_t cap) {
     return n;
 }
 
-static int create_common(qtm_ctx** out, int32_t n_sys, const qtm_system* sys, const qtm_opts* o, bool allow_sparse) {
+static int create_common(qtm_ctx** out, int32_t n_sys, const qtm_system* sys, const qtm_opts* o, bool batch) {
     if (!out) return fail(QTM_E_INVAL, "null output pointer");
     *out = nullptr;
     qtm_opts opt;
@@ -586,9 +593,10 @@ static int create_common(qtm_ctx** out, int32_t n_sys, const qtm_system* sys, co
     c->device = opt.device;
     c->stream = (hipStream_t)opt.stream;
     c->ncu = prop.multiProcessorCount;
+    c->batch = batch;
     c->sys.resize(n_sys);
     for (int s = 0; s < n_sys; ++s) {
-        int rc = setup_system(c->sys[s], sys[s], s, opt, allow_sparse);
+        int rc = setup_system(c->sys[s], sys[s], s, opt, batch);
         if (rc) { qtm_destroy(c); return rc; }
     }
     if (hipMalloc(&c->d_sys, sizeof(qtm::DevSystem) * n_sys) != hipSuccess ||
@@ -611,12 +619,12 @@ static int create_common(qtm_ctx** out, int32_t n_sys, const qtm_system* sys, co
 int qtm_create(qtm_ctx** out, const qtm_op* H, const qtm_op* c_ops, int32_t n_c, const double* psi0,
                const double* tlist, int32_t n_t, const qtm_op* e_ops, int32_t n_e, const qtm_opts* o) {
     qtm_system s{H, c_ops, n_c, psi0, tlist, n_t, e_ops, n_e};
-    return create_common(out, 1, &s, o, true);
+    return create_common(out, 1, &s, o, false);
 }
 
 int qtm_create_batch(qtm_ctx** out, int32_t n_sys, const qtm_system* sys, const qtm_opts* o) {
     if (n_sys < 1 || !sys) return fail(QTM_E_INVAL, "need n_sys >= 1 systems");
-    return create_common(out, n_sys, sys, o, false);
+    return create_common(out, n_sys, sys, o, true);
 }
 
 int qtm_run(qtm_ctx* ctx, int64_t ntraj, uint64_t seed) { return qtm_run_range(ctx, 0, ntraj, seed); }
@@ -689,28 +697,61 @@ int qtm_run_range(qtm_ctx* c, int64_t traj_begin, int64_t count, uint64_t seed) 
 
     qtm::LaunchInfo li{};
     HIPCHECK(hipEventRecord(c->ev0, c->stream));
-    // one launch per system, in system order, on the context's stream
-    for (size_t si = 0; si < c->sys.size(); ++si) {
-        const SysHost& Sx = c->sys[si];
-        qtm::RunArgs as = a;
-        as.sys = c->d_sys + si;
-        as.n_sys = 1;
-        int lr;
-        qtm::LaunchInfo lx{};
-        if (Sx.sparse) {
-            int cols = c->o.tile_cols > 0 ? c->o.tile_cols : (c->o.precision == QTM_PREC_FP32 ? 4 : 2);
-            lr = qtm::launch_sparse(as, Sx.dev, c->o.precision, cols, c->stream, &lx);
-        } else if (Sx.team) {
-            lr = qtm::launch_wave(as, Sx.dev, c->o.precision, c->o.team_waves, c->stream, &lx);
-        } else {
-            int bpc = 0, lds = 0;
-            if (qtm::dense_occupancy(Sx.d, c->o.precision, c->o.tile_cols, &bpc, &lds)) bpc = 1;
-            lr = qtm::launch_dense(as, Sx.dev, Sx.d, c->o.precision, bpc, c->stream, &lx);
+    const bool one_launch = c->batch && c->sys.size() > 1 && (c->o.form & QTM_FORM_BATCHED);
+    if (one_launch) {
+        // every system in one persistent launch of the SpMM kernel: blocks move from
+        // system to system as the trajectory queues run dry
+        int max_d = 0;
+        for (auto& Sx : c->sys) max_d = std::max(max_d, Sx.d);
+        const int cols = c->o.tile_cols > 0 ? c->o.tile_cols : (c->o.precision == QTM_PREC_FP32 ? 4 : 2);
+        int lr = qtm::launch_sparse(a, c->sys[0].dev, max_d, c->o.precision, cols, c->stream, &li);
+        if (lr) return fail(QTM_E_DEVICE, "batch launch failed (%d): %s", lr, hipGetErrorString(hipGetLastError()));
+    } else {
+        // one launch per system; a batch spreads them over side streams so that they overlap
+        const bool fan = c->sys.size() > 1;
+        if (fan && c->side.empty()) {
+            const int ns = (int)std::min<size_t>(8, c->sys.size());
+            c->side.resize(ns, nullptr);
+            c->side_ev.resize(ns, nullptr);
+            for (int i = 0; i < ns; ++i) {
+                HIPCHECK(hipStreamCreateWithFlags(&c->side[i], hipStreamNonBlocking));
+                HIPCHECK(hipEventCreateWithFlags(&c->side_ev[i], hipEventDisableTiming));
+            }
+            HIPCHECK(hipEventCreateWithFlags(&c->fork, hipEventDisableTiming));
         }
-        if (Sx.team && lr == -1) return fail(QTM_E_INVAL, "system %zu: no team shape with %d waves for dimension %d", si, c->o.team_waves, Sx.d);
-        if (Sx.team && lr == -2) return fail(QTM_E_INVAL, "system %zu: the team shape does not fit in LDS (dimension %d)", si, Sx.d);
-        if (lr) return fail(QTM_E_DEVICE, "kernel launch failed for system %zu (%d): %s", si, lr, hipGetErrorString(hipGetLastError()));
-        if (si == 0) li = lx;
+        if (fan) {
+            HIPCHECK(hipEventRecord(c->fork, c->stream));
+            for (auto st : c->side) HIPCHECK(hipStreamWaitEvent(st, c->fork, 0));
+        }
+        for (size_t si = 0; si < c->sys.size(); ++si) {
+            const SysHost& Sx = c->sys[si];
+            hipStream_t st = fan ? c->side[si % c->side.size()] : c->stream;
+            qtm::RunArgs as = a;
+            as.sys = c->d_sys + si;
+            as.n_sys = 1;
+            int lr;
+            qtm::LaunchInfo lx{};
+            if (Sx.sparse) {
+                int cols = c->o.tile_cols > 0 ? c->o.tile_cols : (c->o.precision == QTM_PREC_FP32 ? 4 : 2);
+                lr = qtm::launch_sparse(as, Sx.dev, Sx.d, c->o.precision, cols, st, &lx);
+            } else if (Sx.team) {
+                lr = qtm::launch_wave(as, Sx.dev, c->o.precision, c->o.team_waves, st, &lx);
+            } else {
+                int bpc = 0, lds = 0;
+                if (qtm::dense_occupancy(Sx.d, c->o.precision, c->o.tile_cols, &bpc, &lds)) bpc = 1;
+                lr = qtm::launch_dense(as, Sx.dev, Sx.d, c->o.precision, bpc, st, &lx);
+            }
+            if (Sx.team && lr == -1) return fail(QTM_E_INVAL, "system %zu: no team shape with %d waves for dimension %d", si, c->o.team_waves, Sx.d);
+            if (Sx.team && lr == -2) return fail(QTM_E_INVAL, "system %zu: the team shape does not fit in LDS (dimension %d)", si, Sx.d);
+            if (lr) return fail(QTM_E_DEVICE, "kernel launch failed for system %zu (%d): %s", si, lr, hipGetErrorString(hipGetLastError()));
+            if (si == 0) li = lx;
+        }
+        if (fan) {
+            for (size_t i = 0; i < c->side.size(); ++i) {
+                HIPCHECK(hipEventRecord(c->side_ev[i], c->side[i]));
+                HIPCHECK(hipStreamWaitEvent(c->stream, c->side_ev[i], 0));
+            }
+        }
     }
     HIPCHECK(hipEventRecord(c->ev1, c->stream));
     for (auto& S : c->sys)
@@ -978,6 +1019,9 @@ void qtm_destroy(qtm_ctx* c) {
     if (c->d_cursor) (void)hipFree(c->d_cursor);
     if (c->d_mlp) (void)hipFree(c->d_mlp);
     if (c->d_mlpf) (void)hipFree(c->d_mlpf);
+    for (auto e : c->side_ev) if (e) (void)hipEventDestroy(e);
+    for (auto st : c->side) if (st) (void)hipStreamDestroy(st);
+    if (c->fork) (void)hipEventDestroy(c->fork);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     delete c;

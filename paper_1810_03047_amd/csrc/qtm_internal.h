@@ -87,7 +87,8 @@ struct RunArgs {
 struct LaunchInfo { int blocks, threads, lds, cols, shape; };
 int launch_dense(const RunArgs& a, const DevSystem& s0, int max_d, int prec, int blocks_per_cu,
                  hipStream_t st, LaunchInfo* info);
-int launch_sparse(const RunArgs& a, const DevSystem& s0, int prec, int cols, hipStream_t st, LaunchInfo* info);
+// one launch for the systems a.sys[0 .. a.n_sys) of dimension at most max_d
+int launch_sparse(const RunArgs& a, const DevSystem& s0, int max_d, int prec, int cols, hipStream_t st, LaunchInfo* info);
 // fixed-order trajectory average: partial sums over chunks of trajectories, then
 // the chunks in order; part holds average_part_size(m) doubles
 size_t average_part_size(int m, long long count);

@@ -4,34 +4,61 @@
 
 namespace qtm {
 
+// One launch can serve several systems (a batch of mixed dimension): a block
+// takes the first system whose trajectory queue is not exhausted, runs it with
+// slot refill until its queue runs dry, then moves on.  a.sys_cursor records the
+// first system that may still have work, so finished systems are skipped.
 template <int RPT, int NBC, int PREC>
 __global__ void __launch_bounds__(1024) traj_sparse_kernel(RunArgs a) {
     extern __shared__ double smem[];
     __shared__ int flags[8];
-    const DevSystem& S = a.sys[0];
-    SparseLayout<RPT, NBC, PREC> L;
-    L.S = &S;
-    L.tid = threadIdx.x; L.nthr = blockDim.x; L.lane = threadIdx.x & 63; L.w = threadIdx.x >> 6;
-    L.NW = blockDim.x >> 6; L.d = S.d; L.NB = NBC; L.dp = S.d;
-    char* p = (char*)smem;
-    Col* cs = (Col*)p;
-    p += ((size_t)NBC * sizeof(Col) + 15) & ~(size_t)15;
-    size_t ssz = (size_t)S.d * NBC * sizeof(double2);
-    L.Stage = (double2*)p;
-    L.Stage32 = (float2*)p;
-    p += ssz;
-    L.red = (double*)p;
-    Body<SparseLayout<RPT, NBC, PREC>> B(L, S, a, cs, flags);
-    B.run();
-    if (threadIdx.x == 0) atomicAdd(&a.counters[0], B.passes);
+    __shared__ int cur;
+    unsigned long long passes = 0;
+    int si = 0;
+    for (;;) {
+        if (a.n_sys > 1) {
+            if (threadIdx.x == 0) {
+                int s2 = max(si, (int)__atomic_load_n(a.sys_cursor, __ATOMIC_RELAXED));
+                while (s2 < a.n_sys &&
+                       __atomic_load_n(a.sys[s2].queue, __ATOMIC_RELAXED) >= (unsigned long long)a.sys[s2].count) {
+                    atomicMax(a.sys_cursor, (unsigned int)(s2 + 1));
+                    ++s2;
+                }
+                cur = s2;
+            }
+            __syncthreads();
+            si = cur;
+            if (si >= a.n_sys) break;
+        }
+        const DevSystem& S = a.sys[si];
+        SparseLayout<RPT, NBC, PREC> L;
+        L.S = &S;
+        L.tid = threadIdx.x; L.nthr = blockDim.x; L.lane = threadIdx.x & 63; L.w = threadIdx.x >> 6;
+        L.NW = blockDim.x >> 6; L.d = S.d; L.NB = NBC; L.dp = S.d;
+        char* p = (char*)smem;
+        Col* cs = (Col*)p;
+        p += ((size_t)NBC * sizeof(Col) + 15) & ~(size_t)15;
+        size_t ssz = (size_t)S.d * NBC * sizeof(double2);
+        L.Stage = (double2*)p;
+        L.Stage32 = (float2*)p;
+        p += ssz;
+        L.red = (double*)p;
+        Body<SparseLayout<RPT, NBC, PREC>> B(L, S, a, cs, flags);
+        B.run();
+        passes += B.passes;
+        __syncthreads();                 // the block leaves the system together
+        if (a.n_sys <= 1) break;
+        ++si;
+    }
+    if (threadIdx.x == 0) atomicAdd(&a.counters[0], passes);
 }
 
-int launch_sparse(const RunArgs& a, const DevSystem& s0, int prec, int cols, hipStream_t st, LaunchInfo* info) {
-    int threads = s0.d >= 1024 ? 1024 : ((s0.d + 63) / 64) * 64;
-    int rpt = (s0.d + threads - 1) / threads;
+int launch_sparse(const RunArgs& a, const DevSystem& s0, int max_d, int prec, int cols, hipStream_t st, LaunchInfo* info) {
+    int threads = max_d >= 1024 ? 1024 : ((max_d + 63) / 64) * 64;
+    int rpt = (max_d + threads - 1) / threads;
     if (rpt > 2) return -1;
     if (cols != 1 && cols != 2 && cols != 4) cols = 2;
-    size_t lds = (((size_t)cols * sizeof(Col) + 15) & ~(size_t)15) + (size_t)s0.d * cols * sizeof(double2) +
+    size_t lds = (((size_t)cols * sizeof(Col) + 15) & ~(size_t)15) + (size_t)max_d * cols * sizeof(double2) +
                  (size_t)(threads / 64) * cols * kNVMax * sizeof(double);
     int dev = 0, ncu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return -3;
@@ -49,7 +76,7 @@ int launch_sparse(const RunArgs& a, const DevSystem& s0, int prec, int cols, hip
     int nb = 1;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, threads, lds) != hipSuccess) nb = 1;
     if (nb < 1) nb = 1;
-    long long need = (s0.count + cols - 1) / cols;
+    long long need = ((s0.count + cols - 1) / cols) * (a.n_sys > 0 ? a.n_sys : 1);
     long long blocks = a.persistent ? (long long)ncu * nb : need;
     if (blocks > need) blocks = need;
     if (blocks < 1) blocks = 1;

@@ -149,6 +149,24 @@ def test_batch_mixed_dimension_fp64_exact():
         assert np.max(np.abs(mean - r["mean"])) <= 1e-9, sidx
 
 
+@pytest.mark.parametrize("form", [0, 2])
+def test_hetero_batch_one_launch_and_fanout(form):
+    """Heterogeneous batch (random systems, d = 8 .. 200, 1-4 dense collapse operators):
+    form 2 runs every system in one persistent launch, form 0 one launch per system
+    over side streams; both give the oracle's FP64 trajectories for every system."""
+    systems = w.hetero_batch(n_sys=6, d_min=8, d_max=200, key=5, t_end=5.0, n_t=26)
+    n = 24
+    print(f"[gpu] hetero batch dims={[x.dim for x in systems]} form={form} ntraj={n}", flush=True)
+    ctx = qtm.create_batch(systems, qtm.Opts(record_jumps=32, keep_traj=1, form=form))
+    ctx.run(n, 8)
+    for sidx, s in enumerate(systems):
+        r = oracle.run(s, n, seed=8, sys_id=sidx, jcap=32)
+        jn = np.array([ctx.jumps(i, system=sidx)[2] for i in range(n)])
+        assert np.array_equal(jn, r["jump_counts"]), (sidx, np.nonzero(jn != r["jump_counts"]))
+        X = ctx.traj_expect(sidx)
+        assert np.max(np.abs(X - r["X"])) <= 1e-8, sidx
+
+
 # ------------------------------------------------------------------ learned proposal
 def _bf16(x):
     a = np.asarray(x, dtype=np.float32).copy()
@@ -282,8 +300,11 @@ def test_trained_proposal_gains_over_starting_step_rule():
     tau = np.where(seg[:, 18] > 0, 1.0, seg[:, 16])
     F = seg[:, :16].astype(np.float32)
     T = np.stack([np.log(seg[:, 17]), np.log(np.maximum(tau, 1e-12)), seg[:, 18]], 1).astype(np.float32)
-    losses = gen.train_proposal(F, T, epochs=8, batch=4096, lr=2e-3, seed=0)
-    prop = gen.get_proposal()
+    gen.destroy()
+    trainer = qtm.create_system(s, qtm.Opts())      # starts from the library's initialisation
+    losses = trainer.train_proposal(F, T, epochs=8, batch=4096, lr=2e-3, seed=0)
+    prop = trainer.get_proposal()
+    trainer.destroy()
     res = {}
     for name, form in (("rule", qtm.FORM_BATCHED), ("learned", qtm.FORM_BATCHED | qtm.FORM_LEARNED)):
         ctx = qtm.create_system(s, qtm.Opts(form=form))
