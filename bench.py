@@ -16,7 +16,11 @@ the headline form's throughput; the plain form's is reported beside it.
 
 The roofline entry is for the trajectory kernel (traj_team_kernel): algorithmic
 FLOPs = attempted steps x (6 complex products 8 d^2 + 32 vector operations 4 d),
-divided by the kernel time that HIP events record on the launch stream.
+divided by the kernel's time, which the library takes from device wall-clock
+stamps written on the launch stream just before and after the kernel (graph
+capturable).  HIP events (torch.cuda.Event) on the same stream around each whole
+run are reported beside it as run_event_ms (that span also holds the output
+clearing, the averaging and the read-back of the sums).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--forms plain,best]
 """
@@ -90,11 +94,17 @@ def time_form(qtm, system, opts, steps, warmup, seed0=0, proposal=None):
         ctx.set_proposal(*proposal)
     for i in range(warmup):
         ctx.run(NTRAJ, seed0 + 1000 + i)
-    kms, units, acc, rej, seg = [], 0, 0, 0, 0
+    kms, evms, units, acc, rej, seg = [], [], 0, 0, 0, 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
+        # HIP events on the launch stream (torch's current stream) around the whole run
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
         ctx.run(NTRAJ, seed0 + i)
+        e1.record()
+        e1.synchronize()
+        evms.append(e0.elapsed_time(e1))
         st = ctx.stats()
         kms.append(st["kernel_ms"])
         units += st["accepted"] + st["rejected"]
@@ -105,7 +115,7 @@ def time_form(qtm, system, opts, steps, warmup, seed0=0, proposal=None):
     wall = time.perf_counter() - t0
     info = ctx.stats()
     ctx.destroy()
-    return dict(wall=wall, kernel_ms=float(np.mean(kms)), steps_per_run=units / steps, acc=acc / steps,
+    return dict(wall=wall, kernel_ms=float(np.mean(kms)), run_event_ms=float(np.mean(evms)), steps_per_run=units / steps, acc=acc / steps,
                 rej=rej / steps, segments=seg / steps, launch=info)
 
 
@@ -199,7 +209,7 @@ def main():
                    "ntraj": NTRAJ, "form": best_name or "plain", "parallelism": "trajectories (1 GPU)"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK[prec], "unit": "TFLOP/s",
                      "frac": achieved / PEAK[prec], "traffic": None,
-                     "kernel": "traj_team_kernel", "kernel_ms": head["kernel_ms"],
+                     "kernel": "traj_team_kernel", "kernel_ms": head["kernel_ms"], "run_event_ms": head["run_event_ms"],
                      "flop_per_traj_step": jcm_flops_per_step(d), "traj_steps_per_launch": head["steps_per_run"]},
         "tuned_team_waves": {k: v["team_waves"] for k, v in tuned.items()},
     }

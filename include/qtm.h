@@ -103,7 +103,8 @@ typedef struct {
     int64_t rhs_evals;        /* products M w evaluated (per trajectory-column) */
     int64_t passes;           /* block-wide product passes executed by the kernel */
     int64_t failed_traj;      /* smallest failing trajectory index, -1 if none */
-    double kernel_ms;         /* device time of the trajectory kernel(s) */
+    double kernel_ms;         /* device time of the trajectory kernel(s): device wall-clock stamps
+                                 taken on the launch stream just before and after them */
     double elapsed_ms;        /* host wall time of qtm_run */
     int32_t blocks, threads, tile_cols, lds_bytes;   /* launch configuration used */
     int64_t max_team_passes;  /* most product passes of one trajectory team (the launch's critical

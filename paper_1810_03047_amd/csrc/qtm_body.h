@@ -610,7 +610,7 @@ struct Body {
                         c.tseg = c.t;
                         c.rejected = 0;         // the step controller restarts with the segment
                         uint64_t ctr[4] = {(uint64_t)(S.traj_begin + c.traj), (uint64_t)c.seg, 0, 0};
-                        philox4x64(ctr, A.seed, S.key1);
+                        philox4x64(ctr, S.key0, S.key1);
                         c.r = u53(ctr[0]);
                         c.u = u53(ctr[1]);
                         c.first_acc = 1;

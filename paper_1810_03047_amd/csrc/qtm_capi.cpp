@@ -235,13 +235,20 @@ struct qtm_ctx {
     bool ran = false;
     qtm_stats_t st{};
     long long last_begin = 0, last_count = 0;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
     int ncu = 0;
     bool batch = false;                // created by qtm_create_batch
     // per-system launches of a batch fan out over these streams (default priority)
     std::vector<hipStream_t> side;
     std::vector<hipEvent_t> side_ev;
     hipEvent_t fork = nullptr;
+    // the batched form's captured run (valid for graph_count trajectories)
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    long long graph_count = -1;
+    qtm::LaunchInfo graph_li{};
+    unsigned long long* d_stamp = nullptr;   // [2] wall-clock stamps around the trajectory kernels
+    int wall_khz = 100000;                   // rate of the device wall clock
 };
 
 namespace {
@@ -594,6 +601,10 @@ static int create_common(qtm_ctx** out, int32_t n_sys, const qtm_system* sys, co
     c->stream = (hipStream_t)opt.stream;
     c->ncu = prop.multiProcessorCount;
     c->batch = batch;
+    {
+        int khz = 0;
+        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, opt.device) == hipSuccess && khz > 0) c->wall_khz = khz;
+    }
     c->sys.resize(n_sys);
     for (int s = 0; s < n_sys; ++s) {
         int rc = setup_system(c->sys[s], sys[s], s, opt, batch);
@@ -602,15 +613,12 @@ static int create_common(qtm_ctx** out, int32_t n_sys, const qtm_system* sys, co
     if (hipMalloc(&c->d_sys, sizeof(qtm::DevSystem) * n_sys) != hipSuccess ||
         hipMalloc(&c->d_fail, sizeof(long long)) != hipSuccess ||
         hipMalloc(&c->d_counters, 4 * sizeof(unsigned long long)) != hipSuccess ||
-        hipMalloc(&c->d_cursor, sizeof(unsigned int)) != hipSuccess ||
+        hipMalloc(&c->d_cursor, sizeof(unsigned long long)) != hipSuccess ||
+        hipMalloc(&c->d_stamp, 2 * sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc(&c->d_mlp, sizeof(float) * qtm::kNTotal) != hipSuccess ||
         hipMalloc(&c->d_mlpf, sizeof(unsigned short) * qtm::kMlpFrag) != hipSuccess) {
         qtm_destroy(c);
         return fail(QTM_E_NOMEM, "device allocation failed");
-    }
-    if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
-        qtm_destroy(c);
-        return fail(QTM_E_DEVICE, "hipEventCreate failed");
     }
     *out = c;
     return QTM_OK;
@@ -629,74 +637,28 @@ int qtm_create_batch(qtm_ctx** out, int32_t n_sys, const qtm_system* sys, const 
 
 int qtm_run(qtm_ctx* ctx, int64_t ntraj, uint64_t seed) { return qtm_run_range(ctx, 0, ntraj, seed); }
 
-int qtm_run_range(qtm_ctx* c, int64_t traj_begin, int64_t count, uint64_t seed) {
-    if (check_ctx(c)) return QTM_E_INVAL;
-    if (count < 1 || traj_begin < 0) return fail(QTM_E_INVAL, "need count >= 1 and traj_begin >= 0");
-    if ((c->o.form & QTM_FORM_LEARNED) && !c->have_mlp) return fail(QTM_E_STATE, "learned form requested before qtm_set_proposal");
-    HIPCHECK(hipSetDevice(c->device));
-    auto t0 = std::chrono::steady_clock::now();
-    c->ran = false;
-    const int jcap = c->o.record_jumps, segc = c->o.seg_cap;
+// Everything one run puts on the device after the system table is uploaded:
+// clearing the outputs and counters (fill kernels, so that the sequence can be
+// captured into a graph), the trajectory kernel(s) between two device timestamps, and the
+// fixed-order averages.
+static int enqueue_run(qtm_ctx* c, const qtm::RunArgs& a, long long count, hipStream_t st, qtm::LaunchInfo* li) {
+    const int segc = c->o.seg_cap;
+    auto fill = [&](void* p, size_t bytes, unsigned long long v) {
+        return qtm::launch_fill(p, bytes, v, st) ? fail(QTM_E_DEVICE, "fill kernel launch failed") : QTM_OK;
+    };
+    int rc;
     for (auto& S : c->sys) {
         size_t m = (size_t)S.n_e * S.n_t;
-        int rc;
-        if ((rc = ensure_buf(S.X, sizeof(double2) * m * count))) return rc;
-        if ((rc = ensure_buf(S.tstat, sizeof(int) * 4 * count))) return rc;
-        if ((rc = ensure_buf(S.jn, sizeof(int) * count))) return rc;
-        if ((rc = ensure_buf(S.jt, sizeof(double) * (size_t)std::max(1, jcap) * (jcap ? count : 1)))) return rc;
-        if ((rc = ensure_buf(S.jc, sizeof(int) * (size_t)std::max(1, jcap) * (jcap ? count : 1)))) return rc;
-        if ((rc = ensure_buf(S.segs, sizeof(float) * qtm::kSegRec * (size_t)std::max(1, segc) * (segc ? count : 1)))) return rc;
-        if ((rc = ensure_buf(S.queue, sizeof(unsigned long long)))) return rc;
-        if ((rc = ensure_buf(S.sum, sizeof(double) * 2 * m))) return rc;
-        if ((rc = ensure_buf(S.sumsq, sizeof(double) * m))) return rc;
-        if ((rc = ensure_buf(S.avg_part, sizeof(double) * qtm::average_part_size((int)m, count)))) return rc;
-        HIPCHECK(hipMemsetAsync(S.queue.p, 0, sizeof(unsigned long long), c->stream));
-        HIPCHECK(hipMemsetAsync(S.X.p, 0, sizeof(double2) * m * count, c->stream));
-        HIPCHECK(hipMemsetAsync(S.tstat.p, 0, sizeof(int) * 4 * count, c->stream));
-        if (segc) HIPCHECK(hipMemsetAsync(S.segs.p, 0, sizeof(float) * qtm::kSegRec * segc * count, c->stream));
-        S.dev.X = (double2*)S.X.p;
-        S.dev.tstat = (int*)S.tstat.p;
-        S.dev.jt = (double*)S.jt.p;
-        S.dev.jc = (int*)S.jc.p;
-        S.dev.jn = (int*)S.jn.p;
-        S.dev.segs = (float*)S.segs.p;
-        S.dev.queue = (unsigned long long*)S.queue.p;
-        S.dev.count = count;
-        S.dev.traj_begin = traj_begin;
+        if ((rc = fill(S.queue.p, sizeof(unsigned long long), 0))) return rc;
+        if ((rc = fill(S.X.p, sizeof(double2) * m * count, 0))) return rc;
+        if ((rc = fill(S.tstat.p, sizeof(int) * 4 * count, 0))) return rc;
+        if (segc && (rc = fill(S.segs.p, sizeof(float) * qtm::kSegRec * segc * count, 0))) return rc;
     }
-    std::vector<qtm::DevSystem> ds;
-    for (auto& S : c->sys) ds.push_back(S.dev);
-    HIPCHECK(hipMemcpyAsync(c->d_sys, ds.data(), sizeof(qtm::DevSystem) * ds.size(), hipMemcpyHostToDevice, c->stream));
-    long long fail_init = LLONG_MAX;
-    HIPCHECK(hipMemcpyAsync(c->d_fail, &fail_init, sizeof(long long), hipMemcpyHostToDevice, c->stream));
-    HIPCHECK(hipMemsetAsync(c->d_counters, 0, 4 * sizeof(unsigned long long), c->stream));
-    HIPCHECK(hipMemsetAsync(c->d_cursor, 0, sizeof(unsigned int), c->stream));
+    if ((rc = fill(c->d_fail, sizeof(long long), (unsigned long long)LLONG_MAX))) return rc;
+    if ((rc = fill(c->d_counters, 4 * sizeof(unsigned long long), 0))) return rc;
+    if ((rc = fill(c->d_cursor, sizeof(unsigned long long), 0))) return rc;
 
-    qtm::RunArgs a{};
-    a.sys = c->d_sys;
-    a.n_sys = (int)c->sys.size();
-    a.sys_cursor = c->d_cursor;
-    a.rtol = c->o.rtol;
-    a.atol = c->o.atol;
-    a.max_steps = c->o.max_steps;
-    a.seed = seed;
-    a.jcap = jcap;
-    a.seg_cap = segc;
-    a.learned = (c->o.form & QTM_FORM_LEARNED) ? 1 : 0;
-    a.mlp = c->d_mlp;
-    a.mlpf = c->d_mlpf;
-    a.fail = c->d_fail;
-    a.counters = c->d_counters;
-    a.tile_cols = c->o.tile_cols;
-    a.persistent = (c->o.form & QTM_FORM_BATCHED) ? 1 : 0;
-    const SysHost& S0 = c->sys[0];
-    // failsafe bound on block cycles: every slot may run all its trajectories at max_steps
-    long long per_slot = count;   // worst case (one slot)
-    long long mc = (c->o.max_steps + 4) * 3;
-    a.max_cycles = (per_slot > 0 && mc < LLONG_MAX / (per_slot + 1)) ? mc * (per_slot + 1) : LLONG_MAX;
-
-    qtm::LaunchInfo li{};
-    HIPCHECK(hipEventRecord(c->ev0, c->stream));
+    if (qtm::launch_stamp(c->d_stamp, st)) return fail(QTM_E_DEVICE, "timestamp kernel launch failed");
     const bool one_launch = c->batch && c->sys.size() > 1 && (c->o.form & QTM_FORM_BATCHED);
     if (one_launch) {
         // every system in one persistent launch of the SpMM kernel: blocks move from
@@ -704,7 +666,7 @@ int qtm_run_range(qtm_ctx* c, int64_t traj_begin, int64_t count, uint64_t seed) 
         int max_d = 0;
         for (auto& Sx : c->sys) max_d = std::max(max_d, Sx.d);
         const int cols = c->o.tile_cols > 0 ? c->o.tile_cols : (c->o.precision == QTM_PREC_FP32 ? 4 : 2);
-        int lr = qtm::launch_sparse(a, c->sys[0].dev, max_d, c->o.precision, cols, c->stream, &li);
+        int lr = qtm::launch_sparse(a, c->sys[0].dev, max_d, c->o.precision, cols, st, li);
         if (lr) return fail(QTM_E_DEVICE, "batch launch failed (%d): %s", lr, hipGetErrorString(hipGetLastError()));
     } else {
         // one launch per system; a batch spreads them over side streams so that they overlap
@@ -720,12 +682,12 @@ int qtm_run_range(qtm_ctx* c, int64_t traj_begin, int64_t count, uint64_t seed) 
             HIPCHECK(hipEventCreateWithFlags(&c->fork, hipEventDisableTiming));
         }
         if (fan) {
-            HIPCHECK(hipEventRecord(c->fork, c->stream));
-            for (auto st : c->side) HIPCHECK(hipStreamWaitEvent(st, c->fork, 0));
+            HIPCHECK(hipEventRecord(c->fork, st));
+            for (auto ss : c->side) HIPCHECK(hipStreamWaitEvent(ss, c->fork, 0));
         }
         for (size_t si = 0; si < c->sys.size(); ++si) {
             const SysHost& Sx = c->sys[si];
-            hipStream_t st = fan ? c->side[si % c->side.size()] : c->stream;
+            hipStream_t ss = fan ? c->side[si % c->side.size()] : st;
             qtm::RunArgs as = a;
             as.sys = c->d_sys + si;
             as.n_sys = 1;
@@ -733,33 +695,126 @@ int qtm_run_range(qtm_ctx* c, int64_t traj_begin, int64_t count, uint64_t seed) 
             qtm::LaunchInfo lx{};
             if (Sx.sparse) {
                 int cols = c->o.tile_cols > 0 ? c->o.tile_cols : (c->o.precision == QTM_PREC_FP32 ? 4 : 2);
-                lr = qtm::launch_sparse(as, Sx.dev, Sx.d, c->o.precision, cols, st, &lx);
+                lr = qtm::launch_sparse(as, Sx.dev, Sx.d, c->o.precision, cols, ss, &lx);
             } else if (Sx.team) {
-                lr = qtm::launch_wave(as, Sx.dev, c->o.precision, c->o.team_waves, st, &lx);
+                lr = qtm::launch_wave(as, Sx.dev, c->o.precision, c->o.team_waves, ss, &lx);
             } else {
                 int bpc = 0, lds = 0;
                 if (qtm::dense_occupancy(Sx.d, c->o.precision, c->o.tile_cols, &bpc, &lds)) bpc = 1;
-                lr = qtm::launch_dense(as, Sx.dev, Sx.d, c->o.precision, bpc, st, &lx);
+                lr = qtm::launch_dense(as, Sx.dev, Sx.d, c->o.precision, bpc, ss, &lx);
             }
             if (Sx.team && lr == -1) return fail(QTM_E_INVAL, "system %zu: no team shape with %d waves for dimension %d", si, c->o.team_waves, Sx.d);
             if (Sx.team && lr == -2) return fail(QTM_E_INVAL, "system %zu: the team shape does not fit in LDS (dimension %d)", si, Sx.d);
             if (lr) return fail(QTM_E_DEVICE, "kernel launch failed for system %zu (%d): %s", si, lr, hipGetErrorString(hipGetLastError()));
-            if (si == 0) li = lx;
+            if (si == 0) *li = lx;
         }
         if (fan) {
             for (size_t i = 0; i < c->side.size(); ++i) {
                 HIPCHECK(hipEventRecord(c->side_ev[i], c->side[i]));
-                HIPCHECK(hipStreamWaitEvent(c->stream, c->side_ev[i], 0));
+                HIPCHECK(hipStreamWaitEvent(st, c->side_ev[i], 0));
             }
         }
     }
-    HIPCHECK(hipEventRecord(c->ev1, c->stream));
+    if (qtm::launch_stamp(c->d_stamp + 1, st)) return fail(QTM_E_DEVICE, "timestamp kernel launch failed");
     for (auto& S : c->sys)
-        if (qtm::launch_average(S.dev, (double*)S.avg_part.p, (double*)S.sum.p, (double*)S.sumsq.p, c->stream))
+        if (qtm::launch_average(S.dev, (double*)S.avg_part.p, (double*)S.sum.p, (double*)S.sumsq.p, st))
             return fail(QTM_E_DEVICE, "average kernel launch failed");
+    return QTM_OK;
+}
+
+int qtm_run_range(qtm_ctx* c, int64_t traj_begin, int64_t count, uint64_t seed) {
+    if (check_ctx(c)) return QTM_E_INVAL;
+    if (count < 1 || traj_begin < 0) return fail(QTM_E_INVAL, "need count >= 1 and traj_begin >= 0");
+    if ((c->o.form & QTM_FORM_LEARNED) && !c->have_mlp) return fail(QTM_E_STATE, "learned form requested before qtm_set_proposal");
+    HIPCHECK(hipSetDevice(c->device));
+    auto t0 = std::chrono::steady_clock::now();
+    c->ran = false;
+    const int jcap = c->o.record_jumps, segc = c->o.seg_cap;
+    bool realloc = false;
+    for (auto& S : c->sys) {
+        size_t m = (size_t)S.n_e * S.n_t;
+        int rc;
+        void* before[10] = {S.X.p, S.tstat.p, S.jn.p, S.jt.p, S.jc.p, S.segs.p, S.queue.p, S.sum.p, S.sumsq.p, S.avg_part.p};
+        if ((rc = ensure_buf(S.X, sizeof(double2) * m * count))) return rc;
+        if ((rc = ensure_buf(S.tstat, sizeof(int) * 4 * count))) return rc;
+        if ((rc = ensure_buf(S.jn, sizeof(int) * count))) return rc;
+        if ((rc = ensure_buf(S.jt, sizeof(double) * (size_t)std::max(1, jcap) * (jcap ? count : 1)))) return rc;
+        if ((rc = ensure_buf(S.jc, sizeof(int) * (size_t)std::max(1, jcap) * (jcap ? count : 1)))) return rc;
+        if ((rc = ensure_buf(S.segs, sizeof(float) * qtm::kSegRec * (size_t)std::max(1, segc) * (segc ? count : 1)))) return rc;
+        if ((rc = ensure_buf(S.queue, sizeof(unsigned long long)))) return rc;
+        if ((rc = ensure_buf(S.sum, sizeof(double) * 2 * m))) return rc;
+        if ((rc = ensure_buf(S.sumsq, sizeof(double) * m))) return rc;
+        if ((rc = ensure_buf(S.avg_part, sizeof(double) * qtm::average_part_size((int)m, count)))) return rc;
+        void* after[10] = {S.X.p, S.tstat.p, S.jn.p, S.jt.p, S.jc.p, S.segs.p, S.queue.p, S.sum.p, S.sumsq.p, S.avg_part.p};
+        for (int i = 0; i < 10; ++i) realloc |= before[i] != after[i];
+        S.dev.X = (double2*)S.X.p;
+        S.dev.tstat = (int*)S.tstat.p;
+        S.dev.jt = (double*)S.jt.p;
+        S.dev.jc = (int*)S.jc.p;
+        S.dev.jn = (int*)S.jn.p;
+        S.dev.segs = (float*)S.segs.p;
+        S.dev.queue = (unsigned long long*)S.queue.p;
+        S.dev.count = count;
+        S.dev.traj_begin = traj_begin;
+        S.dev.key0 = seed;
+    }
+    // the system table carries everything that changes from run to run (seed,
+    // trajectory range, output buffers); a captured graph reads it from the device
+    std::vector<qtm::DevSystem> ds;
+    for (auto& S : c->sys) ds.push_back(S.dev);
+    HIPCHECK(hipMemcpyAsync(c->d_sys, ds.data(), sizeof(qtm::DevSystem) * ds.size(), hipMemcpyHostToDevice, c->stream));
+
+    qtm::RunArgs a{};
+    a.sys = c->d_sys;
+    a.n_sys = (int)c->sys.size();
+    a.sys_cursor = c->d_cursor;
+    a.rtol = c->o.rtol;
+    a.atol = c->o.atol;
+    a.max_steps = c->o.max_steps;
+    a.jcap = jcap;
+    a.seg_cap = segc;
+    a.learned = (c->o.form & QTM_FORM_LEARNED) ? 1 : 0;
+    a.mlp = c->d_mlp;
+    a.mlpf = c->d_mlpf;
+    a.fail = c->d_fail;
+    a.counters = c->d_counters;
+    a.tile_cols = c->o.tile_cols;
+    a.persistent = (c->o.form & QTM_FORM_BATCHED) ? 1 : 0;
+    // failsafe bound on block cycles: every slot may run all its trajectories at max_steps
+    long long per_slot = count;   // worst case (one slot)
+    long long mc = (c->o.max_steps + 4) * 3;
+    a.max_cycles = (per_slot > 0 && mc < LLONG_MAX / (per_slot + 1)) ? mc * (per_slot + 1) : LLONG_MAX;
+
+    qtm::LaunchInfo li{};
+    if (c->o.form & QTM_FORM_BATCHED) {
+        // the batched form replays one captured graph per trajectory count
+        if (realloc || c->graph_count != count) {
+            if (c->gexec) { (void)hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }
+            if (c->graph) { (void)hipGraphDestroy(c->graph); c->graph = nullptr; }
+            c->graph_count = -1;
+            if (!c->cap) HIPCHECK(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+            HIPCHECK(hipStreamBeginCapture(c->cap, hipStreamCaptureModeRelaxed));
+            int rc = enqueue_run(c, a, count, c->cap, &li);
+            hipGraph_t g = nullptr;
+            hipError_t ee = hipStreamEndCapture(c->cap, &g);
+            if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
+            if (ee != hipSuccess) return fail(QTM_E_DEVICE, "graph capture failed: %s", hipGetErrorString(ee));
+            c->graph = g;
+            HIPCHECK(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+            c->graph_count = count;
+            c->graph_li = li;
+        }
+        li = c->graph_li;
+        HIPCHECK(hipGraphLaunch(c->gexec, c->stream));
+    } else {
+        int rc = enqueue_run(c, a, count, c->stream, &li);
+        if (rc) return rc;
+    }
     HIPCHECK(hipStreamSynchronize(c->stream));
-    float ms = 0.f;
-    HIPCHECK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    // trajectory kernel(s) time from the two device timestamps around them
+    unsigned long long stamps[2] = {0, 0};
+    HIPCHECK(hipMemcpy(stamps, c->d_stamp, sizeof(stamps), hipMemcpyDeviceToHost));
+    const double ms = (double)(stamps[1] - stamps[0]) / (double)c->wall_khz;
     long long failv = 0;
     unsigned long long ctrs[4];
     HIPCHECK(hipMemcpy(&failv, c->d_fail, sizeof(long long), hipMemcpyDeviceToHost));
@@ -1017,13 +1072,15 @@ void qtm_destroy(qtm_ctx* c) {
     if (c->d_fail) (void)hipFree(c->d_fail);
     if (c->d_counters) (void)hipFree(c->d_counters);
     if (c->d_cursor) (void)hipFree(c->d_cursor);
+    if (c->d_stamp) (void)hipFree(c->d_stamp);
     if (c->d_mlp) (void)hipFree(c->d_mlp);
     if (c->d_mlpf) (void)hipFree(c->d_mlpf);
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    if (c->cap) (void)hipStreamDestroy(c->cap);
     for (auto e : c->side_ev) if (e) (void)hipEventDestroy(e);
     for (auto st : c->side) if (st) (void)hipStreamDestroy(st);
     if (c->fork) (void)hipEventDestroy(c->fork);
-    if (c->ev0) (void)hipEventDestroy(c->ev0);
-    if (c->ev1) (void)hipEventDestroy(c->ev1);
     delete c;
 }
 

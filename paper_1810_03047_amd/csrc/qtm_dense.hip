@@ -158,6 +158,32 @@ int launch_dense(const RunArgs& a, const DevSystem& s0, int max_d, int prec, int
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
+// Fills n 8-byte words with v.  Used instead of hipMemsetAsync so that a run can be
+// captured into a graph.
+__global__ void fill_words_kernel(unsigned long long* p, long long n, unsigned long long v) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// Device timestamp (constant-rate wall clock) for timing a stretch of a stream; a
+// kernel, unlike an event, can be captured into a graph.
+__global__ void stamp_kernel(unsigned long long* t) { t[0] = wall_clock64(); }
+
+int launch_stamp(unsigned long long* t, hipStream_t st) {
+    hipLaunchKernelGGL(stamp_kernel, dim3(1), dim3(1), 0, st, t);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int launch_fill(void* p, size_t bytes, unsigned long long v, hipStream_t st) {
+    if (bytes % 8 != 0) return -1;
+    const long long n = (long long)(bytes / 8);
+    if (n == 0) return 0;
+    long long blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(fill_words_kernel, dim3((unsigned)blocks), dim3(256), 0, st, (unsigned long long*)p, n, v);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
 size_t average_part_size(int m, long long count) { return (size_t)3 * average_chunks(m, count) * m; }
 
 int launch_average(const DevSystem& s, double* part, double* sum, double* sumsq, hipStream_t st) {

@@ -62,6 +62,7 @@ struct DevSystem {
     unsigned long long* queue; // next relative trajectory index to hand out
     long long count;
     long long traj_begin;
+    unsigned long long key0;   // Philox key word 0 (the run's seed)
     unsigned long long key1;   // Philox key word 1 (system index)
 };
 
@@ -71,7 +72,6 @@ struct RunArgs {
     unsigned int* sys_cursor;  // first system that may still have trajectories
     double rtol, atol;
     long long max_steps;
-    unsigned long long seed;
     int jcap, seg_cap;
     int learned;
     const float* mlp;          // [kNTotal] weights (BF16-rounded values), biases, mean, scale
@@ -93,6 +93,10 @@ int launch_sparse(const RunArgs& a, const DevSystem& s0, int max_d, int prec, in
 // the chunks in order; part holds average_part_size(m) doubles
 size_t average_part_size(int m, long long count);
 int launch_average(const DevSystem& s, double* part, double* sum, double* sumsq, hipStream_t st);
+// fills bytes (a multiple of 8) with the 8-byte pattern v (graph-capturable clearing)
+int launch_fill(void* p, size_t bytes, unsigned long long v, hipStream_t st);
+// writes the device wall clock (hipDeviceAttributeWallClockRate kHz) to *t
+int launch_stamp(unsigned long long* t, hipStream_t st);
 int dense_occupancy(int max_d, int prec, int tile_cols, int* blocks_per_cu, int* lds);
 // proposal network (qtm_mlp.hip)
 int launch_mlp_grad(const float* P, const float* feat, const float* tgt, const int* perm, long long base, int n,

@@ -415,7 +415,7 @@ struct Team {
                 else if (natt >= A.max_steps) retire(true);
                 else {
                     uint64_t ctr[4] = {(uint64_t)(S.traj_begin + traj), (uint64_t)seg, 0, 0};
-                    philox4x64(ctr, A.seed, S.key1);
+                    philox4x64(ctr, S.key0, S.key1);
                     r = u53(ctr[0]);
                     u = u53(ctr[1]);
                     first_acc = 1;
