@@ -257,18 +257,57 @@ struct Team {
     // ------------------------------------------------------------ outputs
     // <u|O_o|u>/<u|u> for every lane with omode != 0 (one team reduction per observable)
     QTM_DI void output_round(bool on) {
-        double2 uu[NE];
-        int qi[NE];
+        if (S.any_csr_e || !od_lds) { output_round_staged(on); return; }   // observables not all in LDS
+        // diagonal observables only: each component of u is evaluated once and goes
+        // straight into the norm and the observable sums (no vector kept)
+        const int qb = qbase();
+        for (int o0 = 0; o0 < S.n_e; o0 += 3) {
+            const int no = S.n_e - o0 < 3 ? S.n_e - o0 : 3;
+            const double2* dv0 = Od + (size_t)o0 * d;
+            double p[7];
+#pragma unroll
+            for (int v = 0; v < 7; ++v) p[v] = 0.0;
+#pragma unroll
+            for (int e = 0; e < NE; ++e) {
+                const int q = qb + cst(e);
+                const double2 u = (on && q < d) ? vec_mode(e) : make_double2(0.0, 0.0);
+                const double a2 = cabs2(u);
+                const int qi = q < d ? q : 0;
+                p[6] += a2;
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    if (j < no) {
+                        const double2 v = dv0[(size_t)j * d + qi];
+                        p[2 * j] = fma(v.x, a2, p[2 * j]);
+                        p[2 * j + 1] = fma(v.y, a2, p[2 * j + 1]);
+                    }
+                }
+            }
+            tsum<7>(p);
+            if (on && lg == 0 && wv == 0) {
+#pragma unroll
+                for (int j = 0; j < 3; ++j)
+                    if (j < no) S.X[((size_t)traj * S.n_e + o0 + j) * S.n_t + kk] = make_double2(p[2 * j] / p[6], p[2 * j + 1] / p[6]);
+            }
+        }
+    }
+
+    // general observables (some CSR): u is written to the LDS staging tile as it is
+    // evaluated (no vector kept in registers) and read back for every observable
+    QTM_DI void output_round_staged(bool on) {
         double nn = 0.0;
         const int qb = qbase();
+        team_sync();                        // earlier readers of the staging tile are done
 #pragma unroll
         for (int e = 0; e < NE; ++e) {
             const int q = qb + cst(e);
-            uu[e] = (on && q < d) ? vec_mode(e) : make_double2(0.0, 0.0);
-            qi[e] = q < d ? q : 0;
-            nn += cabs2(uu[e]);
+            if (q < d) {
+                const double2 u = on ? vec_mode(e) : make_double2(0.0, 0.0);
+                St[q * 16 + c16] = u;
+                nn += cabs2(u);
+            }
         }
-        if (S.any_csr_e) stage_vec(uu);
+        team_sync();
         // up to three observables and the norm per team reduction
         for (int o0 = 0; o0 < S.n_e; o0 += 3) {
             double p[7];
@@ -279,24 +318,23 @@ struct Team {
             for (int j = 0; j < 3; ++j) {
                 const int o = o0 + j;
                 if (o >= S.n_e) break;
-                if (S.e_fmt[o] == 2) {
-                    const double2* dv = od_lds ? Od + (size_t)o * d : S.e_val + S.e_doff[o];
+                const bool diag = S.e_fmt[o] == 2;
+                const double2* dv = S.e_val + S.e_doff[o];
+                const int* rp = S.e_rp + (size_t)o * (S.d + 1);
 #pragma unroll
-                    for (int e = 0; e < NE; ++e) {
-                        const double a2 = cabs2(uu[e]);
-                        const double2 v = dv[qi[e]];
+                for (int e = 0; e < NE; ++e) {
+                    const int q = qb + cst(e);
+                    if (q >= d || !on) continue;
+                    const double2 u = St[q * 16 + c16];
+                    if (diag) {
+                        const double a2 = cabs2(u);
+                        const double2 v = dv[q];
                         p[2 * j] = fma(v.x, a2, p[2 * j]);
                         p[2 * j + 1] = fma(v.y, a2, p[2 * j + 1]);
-                    }
-                } else {
-                    const int* rp = S.e_rp + (size_t)o * (S.d + 1);
-#pragma unroll
-                    for (int e = 0; e < NE; ++e) {
-                        int q = comp(e);
-                        if (q < 0 || !on) continue;
-                        double2 Ou = csr_row(rp, S.e_ci, S.e_val, q);
-                        p[2 * j] += uu[e].x * Ou.x + uu[e].y * Ou.y;     // Re conj(u) O u
-                        p[2 * j + 1] += uu[e].x * Ou.y - uu[e].y * Ou.x; // Im conj(u) O u
+                    } else {
+                        const double2 Ou = csr_row(rp, S.e_ci, S.e_val, q);
+                        p[2 * j] += u.x * Ou.x + u.y * Ou.y;     // Re conj(u) O u
+                        p[2 * j + 1] += u.x * Ou.y - u.y * Ou.x; // Im conj(u) O u
                     }
                 }
             }
@@ -312,13 +350,13 @@ struct Team {
         }
     }
 
-    // phase 0: new trajectory (t_k == t); 1: accepted step (t < t_k <= tb) or jump
-    // step (t < t_k < tb); 3: after a jump (t_k == t, current y)
+    // phase 0: new trajectory or segment start after a jump (t_k == t, current y);
+    // 1: accepted step (t < t_k <= tb) or jump step (t < t_k < tb)
     QTM_DI void next_output(int phase) {
         omode = 0;
         if (kk >= S.n_t) return;
         const double tk = tnext;
-        if (phase == 0 && state == ST_NEW) {
+        if (phase == 0 && (state == ST_NEW || state == ST_NEEDK1)) {
             if (tk == t) omode = 1;
         } else if (phase == 1 && action == ACT_ACCEPT) {
             if (tk <= tb) {
@@ -327,8 +365,6 @@ struct Team {
             }
         } else if (phase == 1 && action == ACT_JUMP) {
             if (tk < tb) { omode = 3; oth = (tk - t) / h; }
-        } else if (phase == 3 && action == ACT_POSTJUMP) {
-            if (tk == t) omode = 1;
         }
     }
     QTM_DI void outputs_loop(int phase) {
@@ -400,7 +436,9 @@ struct Team {
                 if (state != ST_EMPTY) retire(true);
                 break;
             }
-            if (team_any(state == ST_NEW)) {
+            // outputs at t_k == t: a new trajectory's first ones, and those at the jump
+            // time of a trajectory that jumped in the previous pass (now at its segment start)
+            if (team_any(state == ST_NEW || state == ST_NEEDK1)) {
 #pragma unroll
                 for (int e = 0; e < NE; ++e) {
                     int q = comp(e);
@@ -876,10 +914,15 @@ struct Team {
     QTM_DI void do_jump() {
         const bool on = action == ACT_JUMP;
         {
-            double2 ps[NE];
+            // psi* = u(theta*), written to the staging tile component by component
+            const int qb = qbase();
+            team_sync();                        // earlier readers of the staging tile are done
 #pragma unroll
-            for (int e = 0; e < NE; ++e) ps[e] = (on && comp(e) >= 0) ? dense_at(e, th) : make_double2(0.0, 0.0);
-            stage_vec(ps);                      // psi* = u(theta*)
+            for (int e = 0; e < NE; ++e) {
+                const int q = qb + cst(e);
+                if (q < d) St[q * 16 + c16] = on ? dense_at(e, th) : make_double2(0.0, 0.0);
+            }
+            team_sync();
         }
         // channel: smallest n with sum_{m<=n} p_m >= u * sum p (two uniform passes)
         double tot = 0.0;
@@ -926,10 +969,9 @@ struct Team {
             }
             njump++;
             t = tb;
-            action = ACT_POSTJUMP;
-        }
-        outputs_loop(3);
-        if (action == ACT_POSTJUMP) {
+            // a new segment; an output time equal to the jump time is recorded from the
+            // post-jump state at the start of the next pass (with the new trajectories'
+            // first outputs), which keeps a single copy of the output code per phase
             action = ACT_NONE;
             seg++;
             seg_rec++;
