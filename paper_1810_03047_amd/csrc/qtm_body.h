@@ -148,11 +148,13 @@ template <> struct MfmaT<0> {
     typedef double in_t; typedef d4 acc_t;
     __device__ static acc_t op(in_t a, in_t b, acc_t c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
     __device__ static const in_t* frag(const DevSystem& s) { return s.Mfrag; }
+    __device__ static const in_t* team(const DevSystem& s) { return s.Mteam; }
 };
 template <> struct MfmaT<1> {
     typedef float in_t; typedef f4 acc_t;
     __device__ static acc_t op(in_t a, in_t b, acc_t c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
     __device__ static const in_t* frag(const DevSystem& s) { return s.Mfrag32; }
+    __device__ static const in_t* team(const DevSystem& s) { return s.Mteam32; }
 };
 
 // Dense layout: wave w handles column tile ct = w / wpc (16 columns, one per

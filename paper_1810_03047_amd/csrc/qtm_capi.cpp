@@ -248,6 +248,11 @@ struct qtm_ctx {
     long long graph_count = -1;
     qtm::LaunchInfo graph_li{};
     unsigned long long* d_stamp = nullptr;   // [2] wall-clock stamps around the trajectory kernels
+    // batches of dense systems (d <= 256): systems ordered by tile class, one launch per class
+    bool tile_classes = false;
+    qtm::DevSystem* d_sys_cls = nullptr;
+    std::vector<int> cls_sys;                // system index of each entry of d_sys_cls
+    int cls_off[3] = {0, 0, 0}, cls_n[3] = {0, 0, 0}, cls_maxd[3] = {0, 0, 0}, cls_maxne[3] = {0, 0, 0};
     int wall_khz = 100000;                   // rate of the device wall clock
 };
 
@@ -332,12 +337,27 @@ int setup_system(SysHost& S, const qtm_system& in, int idx, const qtm_opts& o, b
         if (S.team) {
             if ((rc = upload(S, &D.Mfrag, build_frag_team<double>(M, dp, 0)))) return rc;
             if ((rc = upload(S, &D.Mfrag32, build_frag_team<float>(M, dp, 1)))) return rc;
+            D.Mteam = D.Mfrag;
+            D.Mteam32 = D.Mfrag32;
         } else {
             if ((rc = upload(S, &D.Mfrag, build_frag<double>(M, dp, 0)))) return rc;
             if ((rc = upload(S, &D.Mfrag32, build_frag<float>(M, dp, 1)))) return rc;
+            if (want_ell && d <= 256) {        // batches: the tile-class launch reads the team layout
+                if ((rc = upload(S, &D.Mteam, build_frag_team<double>(M, dp, 0)))) return rc;
+                if ((rc = upload(S, &D.Mteam32, build_frag_team<float>(M, dp, 1)))) return rc;
+            }
         }
     } else {
         D.dp = d;
+        if (want_ell && H->fmt != QTM_FMT_CSR && d <= 256) {
+            // dense system of a batch above the block kernel's range: team layout for the
+            // tile-class launch
+            const int dp = (d + 7) / 8 * 8;
+            D.dp = dp;
+            D.rt = 2 * dp / 16;
+            if ((rc = upload(S, &D.Mteam, build_frag_team<double>(M, dp, 0)))) return rc;
+            if ((rc = upload(S, &D.Mteam32, build_frag_team<float>(M, dp, 1)))) return rc;
+        }
     }
     // sliced ELL: for the SpMM kernel, and for every system of a batch (the single
     // launch over all systems runs on it)
@@ -610,10 +630,32 @@ static int create_common(qtm_ctx** out, int32_t n_sys, const qtm_system* sys, co
         int rc = setup_system(c->sys[s], sys[s], s, opt, batch);
         if (rc) { qtm_destroy(c); return rc; }
     }
+    if (batch && n_sys > 1) {
+        bool all = true;
+        for (int s = 0; s < n_sys; ++s)
+            if (sys[s].H->fmt == QTM_FMT_CSR || c->sys[s].d > 256) all = false;
+        if (all) {
+            c->tile_classes = true;
+            for (int k = 0; k < 3; ++k) {
+                c->cls_off[k] = (int)c->cls_sys.size();
+                for (int s = 0; s < n_sys; ++s)
+                    if (qtm::team_batch_class(c->sys[s].d) == k) {
+                        c->cls_sys.push_back(s);
+                        c->cls_maxd[k] = std::max(c->cls_maxd[k], c->sys[s].d);
+                        c->cls_maxne[k] = std::max(c->cls_maxne[k], c->sys[s].n_e);
+                    }
+                c->cls_n[k] = (int)c->cls_sys.size() - c->cls_off[k];
+            }
+            if (hipMalloc(&c->d_sys_cls, sizeof(qtm::DevSystem) * n_sys) != hipSuccess) {
+                qtm_destroy(c);
+                return fail(QTM_E_NOMEM, "device allocation failed");
+            }
+        }
+    }
     if (hipMalloc(&c->d_sys, sizeof(qtm::DevSystem) * n_sys) != hipSuccess ||
         hipMalloc(&c->d_fail, sizeof(long long)) != hipSuccess ||
         hipMalloc(&c->d_counters, 4 * sizeof(unsigned long long)) != hipSuccess ||
-        hipMalloc(&c->d_cursor, sizeof(unsigned long long)) != hipSuccess ||
+        hipMalloc(&c->d_cursor, 4 * sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc(&c->d_stamp, 2 * sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc(&c->d_mlp, sizeof(float) * qtm::kNTotal) != hipSuccess ||
         hipMalloc(&c->d_mlpf, sizeof(unsigned short) * qtm::kMlpFrag) != hipSuccess) {
@@ -656,11 +698,51 @@ static int enqueue_run(qtm_ctx* c, const qtm::RunArgs& a, long long count, hipSt
     }
     if ((rc = fill(c->d_fail, sizeof(long long), (unsigned long long)LLONG_MAX))) return rc;
     if ((rc = fill(c->d_counters, 4 * sizeof(unsigned long long), 0))) return rc;
-    if ((rc = fill(c->d_cursor, sizeof(unsigned long long), 0))) return rc;
+    if ((rc = fill(c->d_cursor, 4 * sizeof(unsigned long long), 0))) return rc;
 
     if (qtm::launch_stamp(c->d_stamp, st)) return fail(QTM_E_DEVICE, "timestamp kernel launch failed");
     const bool one_launch = c->batch && c->sys.size() > 1 && (c->o.form & QTM_FORM_BATCHED);
-    if (one_launch) {
+    auto ensure_side = [&](size_t want) -> int {
+        if (c->side.size() >= want) return QTM_OK;
+        const size_t old_n = c->side.size();
+        c->side.resize(want, nullptr);
+        c->side_ev.resize(want, nullptr);
+        for (size_t i = old_n; i < want; ++i) {
+            HIPCHECK(hipStreamCreateWithFlags(&c->side[i], hipStreamNonBlocking));
+            HIPCHECK(hipEventCreateWithFlags(&c->side_ev[i], hipEventDisableTiming));
+        }
+        if (!c->fork) HIPCHECK(hipEventCreateWithFlags(&c->fork, hipEventDisableTiming));
+        return QTM_OK;
+    };
+    if (one_launch && c->tile_classes && !(c->o.form & QTM_FORM_LEARNED) && c->o.seg_cap == 0) {
+        // one persistent launch per tile class, the classes side by side: team kernel with
+        // the operator in L2 for d <= 64 and d <= 128, SpMM for d <= 256
+        if ((rc = ensure_side(3))) return rc;
+        HIPCHECK(hipEventRecord(c->fork, st));
+        for (int k = 0; k < 3; ++k) HIPCHECK(hipStreamWaitEvent(c->side[k], c->fork, 0));
+        bool first = true;
+        for (int k = 0; k < 3; ++k) {
+            if (!c->cls_n[k]) continue;
+            qtm::RunArgs ak = a;
+            ak.sys = c->d_sys_cls + c->cls_off[k];
+            ak.n_sys = c->cls_n[k];
+            ak.sys_cursor = (unsigned int*)((unsigned long long*)c->d_cursor + 1 + k);
+            qtm::LaunchInfo lx{};
+            int lr;
+            if (k < 2) {
+                lr = qtm::launch_team_batch(ak, c->cls_maxd[k], c->cls_maxne[k], c->o.precision, c->side[k], &lx);
+            } else {
+                const int cols = c->o.tile_cols > 0 ? c->o.tile_cols : (c->o.precision == QTM_PREC_FP32 ? 4 : 2);
+                lr = qtm::launch_sparse(ak, c->sys[c->cls_sys[c->cls_off[k]]].dev, c->cls_maxd[k], c->o.precision, cols, c->side[k], &lx);
+            }
+            if (lr) return fail(QTM_E_DEVICE, "tile-class launch %d failed (%d): %s", k, lr, hipGetErrorString(hipGetLastError()));
+            if (first) { *li = lx; first = false; }
+        }
+        for (int k = 0; k < 3; ++k) {
+            HIPCHECK(hipEventRecord(c->side_ev[k], c->side[k]));
+            HIPCHECK(hipStreamWaitEvent(st, c->side_ev[k], 0));
+        }
+    } else if (one_launch) {
         // every system in one persistent launch of the SpMM kernel: blocks move from
         // system to system as the trajectory queues run dry
         int max_d = 0;
@@ -671,16 +753,7 @@ static int enqueue_run(qtm_ctx* c, const qtm::RunArgs& a, long long count, hipSt
     } else {
         // one launch per system; a batch spreads them over side streams so that they overlap
         const bool fan = c->sys.size() > 1;
-        if (fan && c->side.empty()) {
-            const int ns = (int)std::min<size_t>(8, c->sys.size());
-            c->side.resize(ns, nullptr);
-            c->side_ev.resize(ns, nullptr);
-            for (int i = 0; i < ns; ++i) {
-                HIPCHECK(hipStreamCreateWithFlags(&c->side[i], hipStreamNonBlocking));
-                HIPCHECK(hipEventCreateWithFlags(&c->side_ev[i], hipEventDisableTiming));
-            }
-            HIPCHECK(hipEventCreateWithFlags(&c->fork, hipEventDisableTiming));
-        }
+        if (fan && (rc = ensure_side(std::min<size_t>(8, c->sys.size())))) return rc;
         if (fan) {
             HIPCHECK(hipEventRecord(c->fork, st));
             for (auto ss : c->side) HIPCHECK(hipStreamWaitEvent(ss, c->fork, 0));
@@ -763,6 +836,11 @@ int qtm_run_range(qtm_ctx* c, int64_t traj_begin, int64_t count, uint64_t seed) 
     std::vector<qtm::DevSystem> ds;
     for (auto& S : c->sys) ds.push_back(S.dev);
     HIPCHECK(hipMemcpyAsync(c->d_sys, ds.data(), sizeof(qtm::DevSystem) * ds.size(), hipMemcpyHostToDevice, c->stream));
+    std::vector<qtm::DevSystem> dsc;
+    if (c->tile_classes) {
+        for (int s2 : c->cls_sys) dsc.push_back(c->sys[s2].dev);
+        HIPCHECK(hipMemcpyAsync(c->d_sys_cls, dsc.data(), sizeof(qtm::DevSystem) * dsc.size(), hipMemcpyHostToDevice, c->stream));
+    }
 
     qtm::RunArgs a{};
     a.sys = c->d_sys;
@@ -1073,6 +1151,7 @@ void qtm_destroy(qtm_ctx* c) {
     if (c->d_counters) (void)hipFree(c->d_counters);
     if (c->d_cursor) (void)hipFree(c->d_cursor);
     if (c->d_stamp) (void)hipFree(c->d_stamp);
+    if (c->d_sys_cls) (void)hipFree(c->d_sys_cls);
     if (c->d_mlp) (void)hipFree(c->d_mlp);
     if (c->d_mlpf) (void)hipFree(c->d_mlpf);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);

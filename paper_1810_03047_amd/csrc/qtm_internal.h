@@ -33,6 +33,8 @@ struct DevSystem {
     const double* Mfrag;       // dense: (2dp)^2 doubles in MFMA A-fragment order (block kernel:
                                // [RT][KB][64]; team kernel: [RT][RT][64][4], permuted columns)
     const float* Mfrag32;      // same, rounded to FP32
+    const double* Mteam;       // team-kernel layout [RT][RT][64][4] (every dense system of a batch)
+    const float* Mteam32;
     const int* sl_off;         // sparse: sliced ELL, 64-row slices; entry offset of each slice
     const int* sl_w;           // width of each slice
     const int* sl_col;         // [slice entries], column-major inside a slice
@@ -107,5 +109,10 @@ int mlp_partial_rows(int n);
 int wave_supported(int d);
 int launch_wave(const RunArgs& a, const DevSystem& s0, int prec, int waves_per_team, hipStream_t st, LaunchInfo* info);
 int team_candidates(int d, int* waves, int cap);
+// a batch's dense systems in one persistent launch per tile class (teams of 4 waves with
+// 2 row tiles per wave for d <= 64, 4 for d <= 128), operator A-fragments read from L2;
+// a.sys holds the class's systems; returns -1 when max_d > 128
+int launch_team_batch(const RunArgs& a, int max_d, int max_ne, int prec, hipStream_t st, LaunchInfo* info);
+int team_batch_class(int d);      // 0, 1, 2 for d <= 64, 128, 256; -1 above (class 2 runs on the SpMM kernel)
 
 }  // namespace qtm

@@ -59,7 +59,9 @@ __device__ __forceinline__ constexpr double dense_coef(int a, int i) {
          : (i == 2 ? 1.0 : i == 3 ? -2.0 : i == 4 ? 1.0 : 0.0);
 }
 
-template <int T, int NWT, int PREC>
+// LEARN = false compiles out the segment-start features and the proposal network
+// (kernels that never run the learned form or record segments).
+template <int T, int NWT, int PREC, bool LEARN = true>
 struct Team {
     typedef typename MfmaT<PREC>::in_t in_t;
     typedef typename std::conditional<PREC == 0, double2, float2>::type kv_t;   // stage vectors
@@ -479,8 +481,8 @@ struct Team {
 #pragma unroll
         for (int e = 0; e < NE; ++e)
             if (state == ST_NEEDK1) k[0][e] = K[e];
-        if (A.learned || A.seg_cap > 0) features();
-        if (!A.learned) {
+        if (LEARN && (A.learned || A.seg_cap > 0)) features();
+        if (!LEARN || !A.learned) {
             // Hairer-Norsett-Wanner starting step, first part: d0 = ||y/sc||, d1 = ||f0/sc||
             double p[2] = {0.0, 0.0};
 #pragma unroll
@@ -1047,6 +1049,91 @@ __global__ void __launch_bounds__(NWT == 1 ? 256 : 64 * NWT) traj_team_kernel(Ru
     if ((threadIdx.x & 63) == 0 && W.wv == 0) {
         atomicAdd(&a.counters[0], W.passes);
         atomicMax(&a.counters[2], W.passes);
+    }
+}
+
+// LDS of a batch block: one team whose operator stays in global memory; tables sized
+// for the largest system of its tile class.
+static __host__ __device__ TeamLds team_lds_batch(int dpmax, int dmax, int nemax, int nwt) {
+    TeamLds L;
+    L.m = 0;
+    L.w = 0;
+    L.x = (size_t)2 * dpmax * 16 * sizeof(double);
+    L.ib = L.x + (size_t)nwt * 16 * kXV * sizeof(double);
+    L.fb = L.ib + 16 * sizeof(unsigned long long);
+    L.team = (L.fb + 16 + 15) & ~(size_t)15;
+    L.od = L.team;
+    L.ft = L.od + (size_t)nemax * dmax * sizeof(double2);
+    L.total = L.ft + (size_t)16 * dmax * sizeof(float);
+    return L;
+}
+
+// A batch's dense systems of one tile class in one persistent launch: the block (one
+// team) takes the first system whose trajectory queue is not exhausted, runs it with
+// slot refill until the queue runs dry, then moves on; a.sys_cursor skips finished
+// systems.  A-fragments of each system's operator are read from global memory (L2).
+template <int T, int NWT, int PREC>
+__global__ void __launch_bounds__(64 * NWT) traj_team_batch_kernel(RunArgs a, int dpmax, int dmax, int nemax) {
+    typedef typename MfmaT<PREC>::in_t in_t;
+    extern __shared__ double smem[];
+    __shared__ int cur;
+    const TeamLds L = team_lds_batch(dpmax, dmax, nemax, NWT);
+    char* base = (char*)smem;
+    unsigned long long passes = 0, pmax = 0;
+    int si = 0;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            int s2 = max(si, (int)__atomic_load_n(a.sys_cursor, __ATOMIC_RELAXED));
+            while (s2 < a.n_sys &&
+                   __atomic_load_n(a.sys[s2].queue, __ATOMIC_RELAXED) >= (unsigned long long)a.sys[s2].count) {
+                atomicMax(a.sys_cursor, (unsigned int)(s2 + 1));
+                ++s2;
+            }
+            cur = s2;
+        }
+        __syncthreads();
+        si = cur;
+        if (si >= a.n_sys) break;
+        const DevSystem& S = a.sys[si];
+        const int od_lds = S.any_csr_e ? 0 : 1;
+        double2* Odl = (double2*)(base + L.od);
+        if (od_lds)
+            for (int o = 0; o < S.n_e; ++o)
+                for (int i = threadIdx.x; i < S.d; i += blockDim.x) Odl[(size_t)o * S.d + i] = S.e_val[S.e_doff[o] + i];
+        float* Ftl = (float*)(base + L.ft);
+        for (int i = threadIdx.x; i < 16 * S.d; i += blockDim.x) {
+            const int q = i >> 4, row = i & 15;
+            const bool have = row < 12 || (row < 14 && S.c_isdiag && row - 12 < S.n_c);
+            Ftl[i] = have ? (float)S.f_diag[(size_t)row * S.d + q] : 0.f;
+        }
+        __syncthreads();
+        Team<T, NWT, PREC, false> W(S, a);
+        W.Mf = MfmaT<PREC>::team(S);
+        W.Wb = (in_t*)(base + L.w);
+        W.St = (double2*)(base + L.w);
+        W.Xb = (double*)(base + L.x);
+        W.Ib = (unsigned long long*)(base + L.ib);
+        W.Fb = (int*)(base + L.fb);
+        W.Od = Odl;
+        W.od_lds = od_lds;
+        W.Ft = Ftl;
+        W.lane = threadIdx.x & 63;
+        W.wv = threadIdx.x >> 6;
+        W.lg = W.lane >> 4;
+        W.c16 = W.lane & 15;
+        W.d = S.d;
+        W.dp = S.dp;
+        W.RT = 2 * S.dp / 16;
+        W.q0 = 8 * T * W.wv + (PREC == 0 ? W.lg : 2 * W.lg);
+        W.run();
+        passes += W.passes;
+        pmax = W.passes > pmax ? W.passes : pmax;
+        __syncthreads();                 // the block leaves the system together
+        ++si;
+    }
+    if (threadIdx.x == 0) {
+        atomicAdd(&a.counters[0], passes);
+        atomicMax(&a.counters[2], pmax);
     }
 }
 
