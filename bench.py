@@ -40,6 +40,30 @@ PEAK = {"fp64": 78.6, "fp32": 157.3}          # TFLOP/s, MI355X dense matrix pea
 NTRAJ = 10_000
 
 
+# HBM traffic of the headline kernel per launch from two rocprofv3 counter passes
+# (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what the same counter
+# reads for a 256 MiB device copy (FETCH x 2.0, WRITE x 1.0).  Valid only for the kernel
+# sources it was measured on: reported as null once their hash differs.
+KERNEL_SOURCES = ["qtm_wave.hip", "qtm_wave_t5x1.hip", "qtm_body.h", "qtm_internal.h"]
+TRAFFIC = {"sources_sha256": None, "fetch_kib": None, "write_kib": None, "fetch_scale": 2.0, "write_scale": 1.0}
+
+
+def kernel_sources_sha() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1810_03047_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    t = TRAFFIC
+    if t["sources_sha256"] is None or t["sources_sha256"] != kernel_sources_sha():
+        return None
+    return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
+
+
 def jcm_flops_per_step(d: int) -> float:
     # six products M w (8 d^2 real flops each, complex) + about 32 complex
     # axpy-type vector operations of 4 d flops (stage sums, error, norms)
@@ -135,6 +159,66 @@ def cpu_baseline(system, target_s: float = 12.0):
                       f"{threads} OpenMP threads, {dt:.1f} s"}
 
 
+def other_workload(a, qtm, w, torch):
+    """Secondary configurations, one JSON line each (same keys):
+    tfim   -- transverse-field Ising chain L = 10 (d = 1024, CSR), 20,000 trajectories,
+              t in [0, 20]; plain FP64 vs batched + FP32 products (SpMM kernel);
+    hetero -- 64 random systems (d 8..256, 1-4 dense jump operators), 500 trajectories
+              each, t in [0, 20]; per-system launches (FP64) vs the batched tile-class
+              launches with FP32 products."""
+    if a.workload == "tfim":
+        target, n, label = w.tfim(), 20_000, "tfim L=10 (d=1024, CSR, nnz 11264), J=1, h=0.8, gamma=0.05, t in [0,20] (201 points), 20000 trajectories"
+        make = lambda o: qtm.create_system(target, o)
+        run = lambda ctx, seed: ctx.run(n, seed)
+        nnz = int(len(target.H.col_ind))          # M = -i H_eff has the pattern of H (its diagonal is stored)
+        flops = lambda st: (st["accepted"] + st["rejected"]) * (6 * 8.0 * nnz + 128.0 * target.dim)
+    else:
+        target, n, label = w.hetero_batch(), 500, "hetero_batch 64 systems d~U{8..256}, n_c~U{1..4}, t in [0,20] (101 points), 500 trajectories each"
+        make = lambda o: qtm.create_batch(target, o)
+        run = lambda ctx, seed: ctx.run(n, seed)
+
+        def flops(st, ctx=None):
+            tot = 0.0
+            for si, sy in enumerate(target):
+                ts = ctx.traj_stats(si)
+                tot += float(ts[:, 0].sum() + ts[:, 1].sum()) * (6 * 8.0 * sy.dim ** 2 + 128.0 * sy.dim)
+            return tot
+    total = n * (len(target) if a.workload == "hetero" else 1)
+    out = {}
+    for name, o in (("plain", qtm.Opts(precision=qtm.PREC_FP64)),
+                    ("best", qtm.Opts(precision=qtm.PREC_FP32, form=qtm.FORM_BATCHED))):
+        ctx = make(o)
+        for i in range(a.warmup):
+            run(ctx, 1000 + i)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        kms, fl = [], []
+        for i in range(a.steps):
+            run(ctx, i)
+            st = ctx.stats()
+            kms.append(st["kernel_ms"])
+            fl.append(flops(st, ctx) if a.workload == "hetero" else flops(st))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        out[name] = dict(value=total * a.steps / wall, ms=wall / a.steps * 1e3, kernel_ms=float(np.mean(kms)),
+                         tflops=float(np.mean(fl)) / (float(np.mean(kms)) * 1e-3) / 1e12)
+        ctx.destroy()
+    b = out["best"]
+    peak = PEAK["fp32"]
+    line = {
+        "metric": METRIC, "value": b["value"], "unit": "trajectories/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": b["ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 products, f64 state", "data": "synthetic",
+        "config": {"workload": label, "ntraj": total, "form": "batched+mixed", "parallelism": "trajectories (1 GPU)"},
+        "roofline": {"bound": "alu" if a.workload == "tfim" else "mfma", "achieved": b["tflops"], "peak": peak,
+                     "unit": "TFLOP/s", "frac": b["tflops"] / peak, "traffic": None,
+                     "kernel": "traj_sparse_kernel" if a.workload == "tfim" else "traj_team_batch_kernel + traj_sparse_kernel",
+                     "kernel_ms": b["kernel_ms"]},
+        "plain": out["plain"], "speedup_vs_plain": b["value"] / out["plain"]["value"],
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -144,6 +228,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--tune-cache", default=None, help="JSON file for the autotuner's choices")
+    ap.add_argument("--workload", default="jcm", choices=["jcm", "tfim", "hetero"],
+                    help="jcm (default, the headline) or a secondary configuration")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: trajectories are independent and the multi-GPU path "
@@ -157,6 +243,9 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if a.workload != "jcm":
+        other_workload(a, qtm, w, torch)
+        return
     system = w.jaynes_cummings()
     d = system.dim
     forms = a.forms.split(",")
@@ -208,7 +297,7 @@ def main():
                                "t in [0,50] (501 points), rtol 1e-6, atol 1e-8, 10000 trajectories",
                    "ntraj": NTRAJ, "form": best_name or "plain", "parallelism": "trajectories (1 GPU)"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK[prec], "unit": "TFLOP/s",
-                     "frac": achieved / PEAK[prec], "traffic": None,
+                     "frac": achieved / PEAK[prec], "traffic": measured_traffic(),
                      "kernel": "traj_team_kernel", "kernel_ms": head["kernel_ms"], "run_event_ms": head["run_event_ms"],
                      "flop_per_traj_step": jcm_flops_per_step(d), "traj_steps_per_launch": head["steps_per_run"]},
         "tuned_team_waves": {k: v["team_waves"] for k, v in tuned.items()},
