@@ -282,7 +282,24 @@ template <int RPT, int NBC, int PREC> struct SparseLayout {
                     double2 acc[NBC];
 #pragma unroll
                     for (int b = 0; b < NBC; ++b) acc[b] = make_double2(0.0, 0.0);
-                    for (int p = 0; p < wd; ++p) {
+                    // entries in groups of four: the group's column and value loads are
+                    // issued together (one memory latency per group, not per entry)
+                    int p = 0;
+                    for (; p + 4 <= wd; p += 4) {
+                        int c[4];
+                        double2 v[4];
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) { const int idx = off + (p + j) * 64 + ln; c[j] = S->sl_col[idx]; v[j] = S->sl_val[idx]; }
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+#pragma unroll
+                            for (int b = 0; b < NBC; ++b) {
+                                double2 x = Stage[c[j] * NBC + b];
+                                acc[b].x = fma(v[j].x, x.x, fma(-v[j].y, x.y, acc[b].x));
+                                acc[b].y = fma(v[j].x, x.y, fma(v[j].y, x.x, acc[b].y));
+                            }
+                    }
+                    for (; p < wd; ++p) {
                         int idx = off + p * 64 + ln;
                         int c = S->sl_col[idx];
                         double2 v = S->sl_val[idx];
@@ -299,7 +316,22 @@ template <int RPT, int NBC, int PREC> struct SparseLayout {
                     float2 acc[NBC];
 #pragma unroll
                     for (int b = 0; b < NBC; ++b) acc[b] = make_float2(0.f, 0.f);
-                    for (int p = 0; p < wd; ++p) {
+                    int p = 0;
+                    for (; p + 4 <= wd; p += 4) {
+                        int c[4];
+                        float2 v[4];
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) { const int idx = off + (p + j) * 64 + ln; c[j] = S->sl_col[idx]; v[j] = S->sl_val32[idx]; }
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+#pragma unroll
+                            for (int b = 0; b < NBC; ++b) {
+                                float2 x = Stage32[c[j] * NBC + b];
+                                acc[b].x = fmaf(v[j].x, x.x, fmaf(-v[j].y, x.y, acc[b].x));
+                                acc[b].y = fmaf(v[j].x, x.y, fmaf(v[j].y, x.x, acc[b].y));
+                            }
+                    }
+                    for (; p < wd; ++p) {
                         int idx = off + p * 64 + ln;
                         int c = S->sl_col[idx];
                         float2 v = S->sl_val32[idx];

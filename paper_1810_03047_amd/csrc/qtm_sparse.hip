@@ -1,15 +1,19 @@
-// qtm_sparse.hip -- trajectory kernel for sparse H_eff: sliced-ELL SpMM, one
-// thread per state component, the column block staged in LDS.
+// qtm_sparse.hip -- trajectory kernel for sparse H_eff: sliced-ELL SpMM, each thread
+// owns RPT state components (rows) of the block's NBC trajectories, the column block
+// staged in LDS.  Blocks of 256 threads: the register file then holds the state
+// without spilling (a 1024-thread block would cap every lane at 128 registers).
 #include "qtm_body.h"
 
 namespace qtm {
+
+constexpr int kSparseThreads = 256;
 
 // One launch can serve several systems (a batch of mixed dimension): a block
 // takes the first system whose trajectory queue is not exhausted, runs it with
 // slot refill until its queue runs dry, then moves on.  a.sys_cursor records the
 // first system that may still have work, so finished systems are skipped.
 template <int RPT, int NBC, int PREC>
-__global__ void __launch_bounds__(1024) traj_sparse_kernel(RunArgs a) {
+__global__ void __launch_bounds__(kSparseThreads) traj_sparse_kernel(RunArgs a) {
     extern __shared__ double smem[];
     __shared__ int flags[8];
     __shared__ int cur;
@@ -53,23 +57,30 @@ __global__ void __launch_bounds__(1024) traj_sparse_kernel(RunArgs a) {
     if (threadIdx.x == 0) atomicAdd(&a.counters[0], passes);
 }
 
+#ifndef QTM_SPARSE_INSTANCES
+// instances (rows per thread x trajectories per block, rows x trajectories <= 8) live in
+// qtm_sparse_r*.hip so that they compile in parallel
+template <int R, int C, int P> const void* sparse_fn_inst();
+
 int launch_sparse(const RunArgs& a, const DevSystem& s0, int max_d, int prec, int cols, hipStream_t st, LaunchInfo* info) {
-    int threads = max_d >= 1024 ? 1024 : ((max_d + 63) / 64) * 64;
+    const int threads = max_d >= kSparseThreads ? kSparseThreads : ((max_d + 63) / 64) * 64;
     int rpt = (max_d + threads - 1) / threads;
-    if (rpt > 2) return -1;
+    if (rpt == 3) rpt = 4;
+    if (rpt > 4 && rpt <= 8) rpt = 8;
+    if (rpt > 8) return -1;
     if (cols != 1 && cols != 2 && cols != 4) cols = 2;
+    while (rpt * cols > 8) cols >>= 1;
     size_t lds = (((size_t)cols * sizeof(Col) + 15) & ~(size_t)15) + (size_t)max_d * cols * sizeof(double2) +
                  (size_t)(threads / 64) * cols * kNVMax * sizeof(double);
     int dev = 0, ncu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return -3;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return -3;
     const void* fn = nullptr;
-#define QTM_SPARSE_CASE(R, C, P) \
-    if (rpt == R && cols == C && prec == P) fn = (const void*)&traj_sparse_kernel<R, C, P>;
-    QTM_SPARSE_CASE(1, 1, 0) QTM_SPARSE_CASE(1, 2, 0) QTM_SPARSE_CASE(1, 4, 0)
-    QTM_SPARSE_CASE(1, 1, 1) QTM_SPARSE_CASE(1, 2, 1) QTM_SPARSE_CASE(1, 4, 1)
-    QTM_SPARSE_CASE(2, 1, 0) QTM_SPARSE_CASE(2, 2, 0) QTM_SPARSE_CASE(2, 4, 0)
-    QTM_SPARSE_CASE(2, 1, 1) QTM_SPARSE_CASE(2, 2, 1) QTM_SPARSE_CASE(2, 4, 1)
+#define QTM_SPARSE_CASE(R, C) \
+    if (rpt == R && cols == C) fn = prec == 0 ? sparse_fn_inst<R, C, 0>() : sparse_fn_inst<R, C, 1>();
+    QTM_SPARSE_CASE(1, 1) QTM_SPARSE_CASE(1, 2) QTM_SPARSE_CASE(1, 4)
+    QTM_SPARSE_CASE(2, 1) QTM_SPARSE_CASE(2, 2) QTM_SPARSE_CASE(2, 4)
+    QTM_SPARSE_CASE(4, 1) QTM_SPARSE_CASE(4, 2) QTM_SPARSE_CASE(8, 1)
 #undef QTM_SPARSE_CASE
     if (!fn) return -1;
     if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) return -3;
@@ -85,5 +96,6 @@ int launch_sparse(const RunArgs& a, const DevSystem& s0, int max_d, int prec, in
     if (info) { info->blocks = (int)blocks; info->threads = threads; info->lds = (int)lds; info->cols = cols; }
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
+#endif  // QTM_SPARSE_INSTANCES
 
 }  // namespace qtm

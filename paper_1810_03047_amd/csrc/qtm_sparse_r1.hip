@@ -1,0 +1,13 @@
+// Instances of the sparse trajectory kernel (rows per thread, trajectories per block): 1x1, 1x2, 1x4.
+#define QTM_SPARSE_INSTANCES
+#include "qtm_sparse.hip"
+
+namespace qtm {
+template <int R, int C, int P> const void* sparse_fn_inst();
+template <> const void* sparse_fn_inst<1, 1, 0>() { return (const void*)&traj_sparse_kernel<1, 1, 0>; }
+template <> const void* sparse_fn_inst<1, 1, 1>() { return (const void*)&traj_sparse_kernel<1, 1, 1>; }
+template <> const void* sparse_fn_inst<1, 2, 0>() { return (const void*)&traj_sparse_kernel<1, 2, 0>; }
+template <> const void* sparse_fn_inst<1, 2, 1>() { return (const void*)&traj_sparse_kernel<1, 2, 1>; }
+template <> const void* sparse_fn_inst<1, 4, 0>() { return (const void*)&traj_sparse_kernel<1, 4, 0>; }
+template <> const void* sparse_fn_inst<1, 4, 1>() { return (const void*)&traj_sparse_kernel<1, 4, 1>; }
+}  // namespace qtm
