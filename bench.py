@@ -45,7 +45,8 @@ NTRAJ = 10_000
 # reads for a 256 MiB device copy (FETCH x 2.0, WRITE x 1.0).  Valid only for the kernel
 # sources it was measured on: reported as null once their hash differs.
 KERNEL_SOURCES = ["qtm_wave.hip", "qtm_wave_t5x1.hip", "qtm_body.h", "qtm_internal.h"]
-TRAFFIC = {"sources_sha256": None, "fetch_kib": None, "write_kib": None, "fetch_scale": 2.0, "write_scale": 1.0}
+TRAFFIC = {"sources_sha256": "0b978f8a875567eee3b1ad942d49a23703104e3fe8b4ccc649fd9fde80c84772",
+           "fetch_kib": 1607.2, "write_kib": 166662.1, "fetch_scale": 2.0, "write_scale": 1.0}
 
 
 def kernel_sources_sha() -> str:
@@ -228,6 +229,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--tune-cache", default=None, help="JSON file for the autotuner's choices")
+    ap.add_argument("--counters", action="store_true",
+                    help="short run for rocprofv3 counter passes: two launches of the headline kernel "
+                         "(FP32 products, batched, 10,000 trajectories) and a 256 MiB device copy for calibration")
     ap.add_argument("--workload", default="jcm", choices=["jcm", "tfim", "hetero"],
                     help="jcm (default, the headline) or a secondary configuration")
     a = ap.parse_args()
@@ -243,6 +247,17 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if a.counters:
+        ctx = qtm.create_system(w.jaynes_cummings(), qtm.Opts(precision=qtm.PREC_FP32, form=qtm.FORM_BATCHED, team_waves=1))
+        for i in range(2):
+            ctx.run(NTRAJ, i)
+        x = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        x.fill_(1.0)
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"counters_run": True, "kernel_ms": ctx.stats()["kernel_ms"], "copy_bytes": 4 * x.numel()}), flush=True)
+        return
     if a.workload != "jcm":
         other_workload(a, qtm, w, torch)
         return

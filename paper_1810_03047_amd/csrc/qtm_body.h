@@ -843,7 +843,7 @@ struct Body {
 #pragma unroll
                 for (int j = 0; j < 7; ++j)
                     if (dp_e(j) != 0.0) er = cfma(h * dp_e(j), to_d2(k[j][e]), er);
-                double sc = A.atol + A.rtol * fmax(sqrt(cabs2(y[e])), sqrt(cabs2(yn[e])));
+                double sc = A.atol + A.rtol * sqrt(fmax(cabs2(y[e]), cabs2(yn[e])));   // = max(|y|, |y_new|): one root
                 p[Ly.slot(e)][0] += cabs2(er) / (sc * sc);
                 p[Ly.slot(e)][1] += cabs2(yn[e]);
             }

@@ -761,7 +761,7 @@ struct Team {
                 int q = comp(e);
                 if (q < 0) continue;
                 double2 er = cscale(h, cfma(dp_e(6), to_d2(k[6][e]), to_d2(es[e])));
-                double sc = A.atol + A.rtol * fmax(sqrt(cabs2(y[e])), sqrt(cabs2(yn[e])));
+                double sc = A.atol + A.rtol * sqrt(fmax(cabs2(y[e]), cabs2(yn[e])));   // = max(|y|, |y_new|): one root
                 p[0] += cabs2(er) / (sc * sc);
                 p[1] += cabs2(yn[e]);
             }
