@@ -715,8 +715,8 @@ static int enqueue_run(qtm_ctx* c, const qtm::RunArgs& a, long long count, hipSt
         return QTM_OK;
     };
     if (one_launch && c->tile_classes && !(c->o.form & QTM_FORM_LEARNED) && c->o.seg_cap == 0) {
-        // one persistent launch per tile class, the classes side by side: team kernel with
-        // the operator in L2 for d <= 64 and d <= 128, SpMM for d <= 256
+        // one persistent launch per tile class (team kernel, operator in L2; d <= 64, 128,
+        // 256), the classes side by side
         if ((rc = ensure_side(3))) return rc;
         HIPCHECK(hipEventRecord(c->fork, st));
         for (int k = 0; k < 3; ++k) HIPCHECK(hipStreamWaitEvent(c->side[k], c->fork, 0));
@@ -728,13 +728,7 @@ static int enqueue_run(qtm_ctx* c, const qtm::RunArgs& a, long long count, hipSt
             ak.n_sys = c->cls_n[k];
             ak.sys_cursor = (unsigned int*)((unsigned long long*)c->d_cursor + 1 + k);
             qtm::LaunchInfo lx{};
-            int lr;
-            if (k < 2) {
-                lr = qtm::launch_team_batch(ak, c->cls_maxd[k], c->cls_maxne[k], c->o.precision, c->side[k], &lx);
-            } else {
-                const int cols = c->o.tile_cols > 0 ? c->o.tile_cols : (c->o.precision == QTM_PREC_FP32 ? 4 : 2);
-                lr = qtm::launch_sparse(ak, c->sys[c->cls_sys[c->cls_off[k]]].dev, c->cls_maxd[k], c->o.precision, cols, c->side[k], &lx);
-            }
+            int lr = qtm::launch_team_batch(ak, c->cls_maxd[k], c->cls_maxne[k], c->o.precision, c->side[k], &lx);
             if (lr) return fail(QTM_E_DEVICE, "tile-class launch %d failed (%d): %s", k, lr, hipGetErrorString(hipGetLastError()));
             if (first) { *li = lx; first = false; }
         }

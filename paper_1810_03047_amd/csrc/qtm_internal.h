@@ -110,9 +110,9 @@ int wave_supported(int d);
 int launch_wave(const RunArgs& a, const DevSystem& s0, int prec, int waves_per_team, hipStream_t st, LaunchInfo* info);
 int team_candidates(int d, int* waves, int cap);
 // a batch's dense systems in one persistent launch per tile class (teams of 4 waves with
-// 2 row tiles per wave for d <= 64, 4 for d <= 128), operator A-fragments read from L2;
-// a.sys holds the class's systems; returns -1 when max_d > 128
+// 2, 4 or 8 row tiles per wave for d <= 64, 128, 256), operator A-fragments read from L2;
+// a.sys holds the class's systems; returns -1 when max_d > 256
 int launch_team_batch(const RunArgs& a, int max_d, int max_ne, int prec, hipStream_t st, LaunchInfo* info);
-int team_batch_class(int d);      // 0, 1, 2 for d <= 64, 128, 256; -1 above (class 2 runs on the SpMM kernel)
+int team_batch_class(int d);      // 0, 1, 2 for d <= 64, 128, 256; -1 above
 
 }  // namespace qtm
