@@ -133,6 +133,21 @@ struct Col {
 // lg + 4 i (i = 0..3) to lane group lg, the FP32 one rows 4 lg + i; the row
 // order is chosen per precision so that a lane always holds (re, im) of two
 // whole components: acc = (Re q0, Im q0, Re q1, Im q1).
+// Loads through pointers known to address global memory.  Pointers read from the
+// LDS copy of the system descriptor are otherwise generic, and a generic (flat)
+// load waits on the LDS counter as well.
+typedef double gd2_t __attribute__((ext_vector_type(2)));
+typedef float gf2_t __attribute__((ext_vector_type(2)));
+QTM_DI int gload(const int* p, int i) { return ((const __attribute__((address_space(1))) int*)p)[i]; }
+QTM_DI double2 gload(const double2* p, int i) {
+    const gd2_t v = ((const __attribute__((address_space(1))) gd2_t*)p)[i];
+    return make_double2(v.x, v.y);
+}
+QTM_DI float2 gload(const float2* p, int i) {
+    const gf2_t v = ((const __attribute__((address_space(1))) gf2_t*)p)[i];
+    return make_float2(v.x, v.y);
+}
+
 template <int PREC> struct RowMap;
 template <> struct RowMap<0> {
     __device__ static int comp(int rt, int lg, int m) { return 8 * rt + lg + 4 * m; }
@@ -257,10 +272,78 @@ template <int RPT, int NBC, int PREC> struct SparseLayout {
     double2* Stage;                     // LDS: [d][NB] complex (FP64) staging
     float2* Stage32;                    // LDS alias for FP32 products
     double* red;                        // LDS: [NW][NB][kNVMax]
+    // LDS-resident sliced ELL (when ell_lds): values, 16-bit columns, slice offsets and widths
+    int ell_lds;
+    const double2* lval;
+    const float2* lval32;
+    const unsigned short* lcol;
+    const int* lsoff;
+    const int* lsw;
+    typedef typename std::conditional<PREC == 0, double2, float2>::type vt_t;   // product arithmetic
+
+    QTM_DI const vt_t* lvals() const { return PREC == 0 ? (const vt_t*)lval : (const vt_t*)lval32; }
+    QTM_DI vt_t stage_at(int i) const { return PREC == 0 ? ((const vt_t*)Stage)[i] : ((const vt_t*)Stage32)[i]; }
 
     QTM_DI int comp(int e) const { int q = tid + (e / NBC) * nthr; return q < d ? q : -1; }
     QTM_DI int slot(int e) const { return e % NBC; }
     QTM_DI int gcol(int s) const { return s; }
+
+    // NR rows (r0 .. r0+NR-1 of this thread) of K = M W over the block's NBC columns.
+    // LDSM: the sliced ELL is resident in LDS; otherwise it is read from global
+    // memory.  Slice widths are multiples of four (zero-valued padding).  The 64 rows
+    // of a wavefront share one slice (blocks are a multiple of 64 threads), so offsets
+    // and widths are wave-uniform.  Entries go in groups of four per row, the NR rows'
+    // groups side by side: all their column and value loads are issued together, then
+    // all staged-vector reads, then the arithmetic.  A row whose slice is narrower than
+    // the widest re-reads its first group with the values zeroed.
+    template <bool LDSM, int NR> QTM_DI void rows(int r0, vt_t (&acc)[NR][NBC]) const {
+        int off[NR], wd[NR], wmax = 0;
+        const int ln = tid & 63;
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            const int sl = (tid + (r0 + i) * nthr) >> 6;
+            const bool in = sl * 64 < d;            // wave-uniform: the slice exists
+            off[i] = __builtin_amdgcn_readfirstlane(in ? (LDSM ? lsoff[sl] : gload(S->sl_off, sl)) : 0);
+            wd[i] = __builtin_amdgcn_readfirstlane(in ? (LDSM ? lsw[sl] : gload(S->sl_w, sl)) : 0);
+            wmax = wd[i] > wmax ? wd[i] : wmax;
+#pragma unroll
+            for (int b = 0; b < NBC; ++b) { acc[i][b].x = 0; acc[i][b].y = 0; }
+        }
+        const vt_t* gval = PREC == 0 ? (const vt_t*)S->sl_val : (const vt_t*)S->sl_val32;
+        const int* gcol = S->sl_col;
+        for (int p = 0; p < wmax; p += 4) {
+            int c[NR][4];
+            vt_t v[NR][4];
+#pragma unroll
+            for (int i = 0; i < NR; ++i) {
+                const bool live = p < wd[i];
+                const int base = off[i] + (live ? p : 0) * 64 + ln;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int idx = base + j * 64;
+                    c[i][j] = LDSM ? (int)lcol[idx] : gload(gcol, idx);
+                    v[i][j] = LDSM ? lvals()[idx] : gload(gval, idx);
+                    if (!live) { v[i][j].x = 0; v[i][j].y = 0; }
+                }
+            }
+            vt_t x[NR][4][NBC];
+#pragma unroll
+            for (int i = 0; i < NR; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+#pragma unroll
+                    for (int b = 0; b < NBC; ++b) x[i][j][b] = stage_at(c[i][j] * NBC + b);
+#pragma unroll
+            for (int i = 0; i < NR; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+#pragma unroll
+                    for (int b = 0; b < NBC; ++b) {
+                        acc[i][b].x = fma(v[i][j].x, x[i][j][b].x, fma(-v[i][j].y, x[i][j][b].y, acc[i][b].x));
+                        acc[i][b].y = fma(v[i][j].x, x[i][j][b].y, fma(v[i][j].y, x[i][j][b].x, acc[i][b].y));
+                    }
+        }
+    }
 
     QTM_DI void rhs(const double2 (&W)[NE], kv_t (&K)[NE]) {
 #pragma unroll
@@ -272,82 +355,18 @@ template <int RPT, int NBC, int PREC> struct SparseLayout {
             }
         }
         __syncthreads();
+        constexpr int NR = (PREC == 1 && RPT >= 2) ? 2 : 1;   // FP64: register room for one row only
 #pragma unroll
-        for (int r = 0; r < RPT; ++r) {
-            int q = tid + r * nthr;
-            if (q < d) {
-                int sl = q >> 6, ln = q & 63;
-                int off = S->sl_off[sl], wd = S->sl_w[sl];
-                if (PREC == 0) {
-                    double2 acc[NBC];
+        for (int r = 0; r < RPT; r += NR) {
+            vt_t acc[NR][NBC];
+            if (ell_lds) rows<true, NR>(r, acc);
+            else rows<false, NR>(r, acc);
 #pragma unroll
-                    for (int b = 0; b < NBC; ++b) acc[b] = make_double2(0.0, 0.0);
-                    // entries in groups of four: the group's column and value loads are
-                    // issued together (one memory latency per group, not per entry)
-                    int p = 0;
-                    for (; p + 4 <= wd; p += 4) {
-                        int c[4];
-                        double2 v[4];
+            for (int i = 0; i < NR; ++i) {
+                const bool in = tid + (r + i) * nthr < d;
 #pragma unroll
-                        for (int j = 0; j < 4; ++j) { const int idx = off + (p + j) * 64 + ln; c[j] = S->sl_col[idx]; v[j] = S->sl_val[idx]; }
-#pragma unroll
-                        for (int j = 0; j < 4; ++j)
-#pragma unroll
-                            for (int b = 0; b < NBC; ++b) {
-                                double2 x = Stage[c[j] * NBC + b];
-                                acc[b].x = fma(v[j].x, x.x, fma(-v[j].y, x.y, acc[b].x));
-                                acc[b].y = fma(v[j].x, x.y, fma(v[j].y, x.x, acc[b].y));
-                            }
-                    }
-                    for (; p < wd; ++p) {
-                        int idx = off + p * 64 + ln;
-                        int c = S->sl_col[idx];
-                        double2 v = S->sl_val[idx];
-#pragma unroll
-                        for (int b = 0; b < NBC; ++b) {
-                            double2 x = Stage[c * NBC + b];
-                            acc[b].x = fma(v.x, x.x, fma(-v.y, x.y, acc[b].x));
-                            acc[b].y = fma(v.x, x.y, fma(v.y, x.x, acc[b].y));
-                        }
-                    }
-#pragma unroll
-                    for (int b = 0; b < NBC; ++b) K[r * NBC + b] = from_d2<kv_t>(acc[b]);
-                } else {
-                    float2 acc[NBC];
-#pragma unroll
-                    for (int b = 0; b < NBC; ++b) acc[b] = make_float2(0.f, 0.f);
-                    int p = 0;
-                    for (; p + 4 <= wd; p += 4) {
-                        int c[4];
-                        float2 v[4];
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) { const int idx = off + (p + j) * 64 + ln; c[j] = S->sl_col[idx]; v[j] = S->sl_val32[idx]; }
-#pragma unroll
-                        for (int j = 0; j < 4; ++j)
-#pragma unroll
-                            for (int b = 0; b < NBC; ++b) {
-                                float2 x = Stage32[c[j] * NBC + b];
-                                acc[b].x = fmaf(v[j].x, x.x, fmaf(-v[j].y, x.y, acc[b].x));
-                                acc[b].y = fmaf(v[j].x, x.y, fmaf(v[j].y, x.x, acc[b].y));
-                            }
-                    }
-                    for (; p < wd; ++p) {
-                        int idx = off + p * 64 + ln;
-                        int c = S->sl_col[idx];
-                        float2 v = S->sl_val32[idx];
-#pragma unroll
-                        for (int b = 0; b < NBC; ++b) {
-                            float2 x = Stage32[c * NBC + b];
-                            acc[b].x = fmaf(v.x, x.x, fmaf(-v.y, x.y, acc[b].x));
-                            acc[b].y = fmaf(v.x, x.y, fmaf(v.y, x.x, acc[b].y));
-                        }
-                    }
-#pragma unroll
-                    for (int b = 0; b < NBC; ++b) K[r * NBC + b] = from_d2<kv_t>(make_double2(acc[b].x, acc[b].y));
-                }
-            } else {
-#pragma unroll
-                for (int b = 0; b < NBC; ++b) K[r * NBC + b] = from_d2<kv_t>(make_double2(0.0, 0.0));
+                for (int b = 0; b < NBC; ++b)
+                    K[(r + i) * NBC + b] = in ? from_d2<kv_t>(make_double2(acc[i][b].x, acc[i][b].y)) : from_d2<kv_t>(make_double2(0.0, 0.0));
             }
         }
         __syncthreads();
@@ -516,8 +535,83 @@ struct Body {
         __syncthreads();
     }
 
+    // All observables diagonal: |u_q|^2 of every element is formed once per round
+    // (a2, zero for columns without an output) and feeds the norm and each of the
+    // group's G observables; one block reduction of 1 + 2G values per group.
+    template <int G> QTM_DI void output_group_diag(int e0, const double (&a2)[L::NE]) {
+        constexpr int NV = 1 + 2 * G;
+        double p[L::CPT][NV];
+#pragma unroll
+        for (int b = 0; b < L::CPT; ++b)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) p[b][v] = 0.0;
+#pragma unroll
+        for (int e = 0; e < L::NE; ++e) p[Ly.slot(e)][0] += a2[e];
+        // the values of observable g + 1 are loaded while g accumulates (indices
+        // clamped to the last observable, so every load is in range)
+        const int last = S.n_e - 1;
+        double2 cur[L::NE], nxt[L::NE];
+        {
+            const double2* dv = S.e_val + S.e_doff[e0 < last ? e0 : last];
+#pragma unroll
+            for (int e = 0; e < L::NE; ++e) { const int q = Ly.comp(e); cur[e] = gload(dv, q >= 0 ? q : 0); }
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            if (g + 1 < G) {
+                const int on = e0 + g + 1;
+                const double2* dv = S.e_val + S.e_doff[on < last ? on : last];
+#pragma unroll
+                for (int e = 0; e < L::NE; ++e) { const int q = Ly.comp(e); nxt[e] = gload(dv, q >= 0 ? q : 0); }
+            }
+            if (e0 + g <= last) {
+#pragma unroll
+                for (int e = 0; e < L::NE; ++e) {
+                    p[Ly.slot(e)][1 + 2 * g] += cur[e].x * a2[e];
+                    p[Ly.slot(e)][2 + 2 * g] += cur[e].y * a2[e];
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < L::NE; ++e) cur[e] = nxt[e];
+        }
+        Ly.template reduce<NV>(p);
+        const int tid = threadIdx.x;
+        if (tid < Ly.NB) {
+            Col& c = cs[tid];
+            if (c.omode) {
+                const double nn = Ly.red_sum(tid, 0);
+                for (int g = 0; g < G && e0 + g < S.n_e; ++g) {
+                    const double re = Ly.red_sum(tid, 1 + 2 * g) / nn;
+                    const double im = Ly.red_sum(tid, 2 + 2 * g) / nn;
+                    S.X[((size_t)c.traj * S.n_e + e0 + g) * S.n_t + c.kk] = make_double2(re, im);
+                }
+            }
+        }
+        __syncthreads();
+    }
+
     QTM_DI void output_round() {
-        if (S.any_csr_e) stage_mode();
+        // the single-pass diagonal path for FP32 products; with FP64 stage vectors its
+        // extra live registers cost more in the stage code than it saves here
+        if (sizeof(kv_t) == 8 && !S.any_csr_e) {
+            double a2[L::NE];
+#pragma unroll
+            for (int e = 0; e < L::NE; ++e) {
+                const int q = Ly.comp(e), gc = Ly.gcol(Ly.slot(e));
+                a2[e] = 0.0;
+                if (q >= 0 && gc >= 0) {
+                    const Col& c = cs[gc];
+                    if (c.omode) a2[e] = cabs2(vec_mode(e, c));
+                }
+            }
+            // groups of up to 7 observables (15 reduced values)
+            for (int e0 = 0; e0 < S.n_e;) {
+                if (S.n_e - e0 <= 3) { output_group_diag<3>(e0, a2); e0 += 3; }
+                else { output_group_diag<7>(e0, a2); e0 += 7; }
+            }
+            return;
+        }
+        stage_mode();
         for (int e0 = 0; e0 < S.n_e;) {
             if (S.n_e - e0 <= 2 || L::GMAX == 2) { output_group<2>(e0); e0 += 2; }
             else { output_group<(L::GMAX > 2 ? L::GMAX : 2)>(e0); e0 += L::GMAX; }

@@ -367,8 +367,8 @@ int setup_system(SysHost& S, const qtm_system& in, int idx, const qtm_opts& o, b
         for (int s = 0; s < nsl; ++s) {
             int w = 0;
             for (int i = 64 * s; i < std::min(d, 64 * s + 64); ++i) w = std::max(w, M.rp[i + 1] - M.rp[i]);
-            wd[s] = w;
-            off[s + 1] = off[s] + 64 * w;
+            wd[s] = (w + 3) & ~3;         // the kernel takes entries in groups of four
+            off[s + 1] = off[s] + 64 * wd[s];
         }
         std::vector<int> col(off[nsl], 0);
         std::vector<double2> val(off[nsl], make_double2(0.0, 0.0));
@@ -386,6 +386,7 @@ int setup_system(SysHost& S, const qtm_system& in, int idx, const qtm_opts& o, b
                 for (int k = M.rp[i + 1] - M.rp[i]; k < wd[s]; ++k) col[off[s] + k * 64 + ln] = i;
             }
         // rows past d in the last slice point at row 0 with zero values
+        D.ell_n = off[nsl];
         if ((rc = upload(S, &D.sl_off, off))) return rc;
         if ((rc = upload(S, &D.sl_w, wd))) return rc;
         if ((rc = upload(S, &D.sl_col, col))) return rc;
@@ -740,9 +741,10 @@ static int enqueue_run(qtm_ctx* c, const qtm::RunArgs& a, long long count, hipSt
         // every system in one persistent launch of the SpMM kernel: blocks move from
         // system to system as the trajectory queues run dry
         int max_d = 0;
-        for (auto& Sx : c->sys) max_d = std::max(max_d, Sx.d);
+        long long max_ell = 0;
+        for (auto& Sx : c->sys) { max_d = std::max(max_d, Sx.d); max_ell = std::max(max_ell, Sx.dev.ell_n); }
         const int cols = c->o.tile_cols > 0 ? c->o.tile_cols : (c->o.precision == QTM_PREC_FP32 ? 4 : 2);
-        int lr = qtm::launch_sparse(a, c->sys[0].dev, max_d, c->o.precision, cols, st, li);
+        int lr = qtm::launch_sparse(a, c->sys[0].dev, max_d, max_ell, c->o.precision, cols, st, li);
         if (lr) return fail(QTM_E_DEVICE, "batch launch failed (%d): %s", lr, hipGetErrorString(hipGetLastError()));
     } else {
         // one launch per system; a batch spreads them over side streams so that they overlap
@@ -762,7 +764,7 @@ static int enqueue_run(qtm_ctx* c, const qtm::RunArgs& a, long long count, hipSt
             qtm::LaunchInfo lx{};
             if (Sx.sparse) {
                 int cols = c->o.tile_cols > 0 ? c->o.tile_cols : (c->o.precision == QTM_PREC_FP32 ? 4 : 2);
-                lr = qtm::launch_sparse(as, Sx.dev, Sx.d, c->o.precision, cols, ss, &lx);
+                lr = qtm::launch_sparse(as, Sx.dev, Sx.d, Sx.dev.ell_n, c->o.precision, cols, ss, &lx);
             } else if (Sx.team) {
                 lr = qtm::launch_wave(as, Sx.dev, c->o.precision, c->o.team_waves, ss, &lx);
             } else {

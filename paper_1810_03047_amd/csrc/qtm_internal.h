@@ -40,6 +40,7 @@ struct DevSystem {
     const int* sl_col;         // [slice entries], column-major inside a slice
     const double2* sl_val;
     const float2* sl_val32;
+    long long ell_n;           // entries of the sliced ELL (sum over slices of 64 x width)
     // collapse operators (CSR, concatenated; row pointers absolute)
     const int* c_rp;           // [n_c][d+1]
     const int* c_ci;
@@ -83,6 +84,7 @@ struct RunArgs {
     long long max_cycles;      // failsafe bound on block cycles
     int tile_cols;             // requested columns per block (0: as many as the waves allow)
     int persistent;            // refill free slots from the queue
+    int ell_lds;               // sparse kernel: the sliced ELL of each system is copied into LDS
 };
 
 // Host-side launchers (defined in qtm_kernels.hip).
@@ -90,7 +92,10 @@ struct LaunchInfo { int blocks, threads, lds, cols, shape; };
 int launch_dense(const RunArgs& a, const DevSystem& s0, int max_d, int prec, int blocks_per_cu,
                  hipStream_t st, LaunchInfo* info);
 // one launch for the systems a.sys[0 .. a.n_sys) of dimension at most max_d
-int launch_sparse(const RunArgs& a, const DevSystem& s0, int max_d, int prec, int cols, hipStream_t st, LaunchInfo* info);
+// (max_ell: most sliced-ELL entries of one of them; the ELL goes into LDS when it fits
+// there without lowering the occupancy)
+int launch_sparse(const RunArgs& a, const DevSystem& s0, int max_d, long long max_ell, int prec, int cols,
+                  hipStream_t st, LaunchInfo* info);
 // fixed-order trajectory average: partial sums over chunks of trajectories, then
 // the chunks in order; part holds average_part_size(m) doubles
 size_t average_part_size(int m, long long count);

@@ -17,6 +17,7 @@ __global__ void __launch_bounds__(kSparseThreads) traj_sparse_kernel(RunArgs a) 
     extern __shared__ double smem[];
     __shared__ int flags[8];
     __shared__ int cur;
+    __shared__ DevSystem sys_lds;
     unsigned long long passes = 0;
     int si = 0;
     for (;;) {
@@ -34,7 +35,15 @@ __global__ void __launch_bounds__(kSparseThreads) traj_sparse_kernel(RunArgs a) 
             si = cur;
             if (si >= a.n_sys) break;
         }
-        const DevSystem& S = a.sys[si];
+        // the system descriptor is read all through the run: a copy in LDS turns every
+        // field access into an LDS read instead of a dependent global load
+        {
+            const unsigned long long* src = (const unsigned long long*)(a.sys + si);
+            unsigned long long* dst = (unsigned long long*)&sys_lds;
+            for (int i = threadIdx.x; i < (int)(sizeof(DevSystem) / 8); i += blockDim.x) dst[i] = src[i];
+        }
+        __syncthreads();
+        const DevSystem& S = sys_lds;
         SparseLayout<RPT, NBC, PREC> L;
         L.S = &S;
         L.tid = threadIdx.x; L.nthr = blockDim.x; L.lane = threadIdx.x & 63; L.w = threadIdx.x >> 6;
@@ -47,6 +56,35 @@ __global__ void __launch_bounds__(kSparseThreads) traj_sparse_kernel(RunArgs a) 
         L.Stage32 = (float2*)p;
         p += ssz;
         L.red = (double*)p;
+        p += (size_t)L.NW * NBC * kNVMax * sizeof(double);
+        L.ell_lds = a.ell_lds;
+        if (a.ell_lds) {
+            // the operator's sliced ELL, resident for the whole system: values, then
+            // 16-bit columns, then slice offsets and widths (sized per system; the launch
+            // reserves room for the largest)
+            const int nsl = (S.d + 63) >> 6;
+            const int n = (int)S.ell_n;
+            typedef typename std::conditional<PREC == 0, double2, float2>::type v_t;
+            v_t* lv = (v_t*)p;
+            p += ((size_t)n * sizeof(v_t) + 15) & ~(size_t)15;
+            unsigned short* lc = (unsigned short*)p;
+            p += ((size_t)n * 2 + 15) & ~(size_t)15;
+            int* lo = (int*)p;
+            int* lw = lo + nsl + 1;
+            for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                if (PREC == 0) ((double2*)lv)[i] = S.sl_val[i];
+                else ((float2*)lv)[i] = S.sl_val32[i];
+                lc[i] = (unsigned short)S.sl_col[i];
+            }
+            for (int i = threadIdx.x; i <= nsl; i += blockDim.x) lo[i] = S.sl_off[i];
+            for (int i = threadIdx.x; i < nsl; i += blockDim.x) lw[i] = S.sl_w[i];
+            L.lval = (const double2*)lv;
+            L.lval32 = (const float2*)lv;
+            L.lcol = lc;
+            L.lsoff = lo;
+            L.lsw = lw;
+            __syncthreads();
+        }
         Body<SparseLayout<RPT, NBC, PREC>> B(L, S, a, cs, flags);
         B.run();
         passes += B.passes;
@@ -62,7 +100,9 @@ __global__ void __launch_bounds__(kSparseThreads) traj_sparse_kernel(RunArgs a) 
 // qtm_sparse_r*.hip so that they compile in parallel
 template <int R, int C, int P> const void* sparse_fn_inst();
 
-int launch_sparse(const RunArgs& a, const DevSystem& s0, int max_d, int prec, int cols, hipStream_t st, LaunchInfo* info) {
+int launch_sparse(const RunArgs& a0, const DevSystem& s0, int max_d, long long max_ell, int prec, int cols,
+                  hipStream_t st, LaunchInfo* info) {
+    RunArgs a = a0;
     const int threads = max_d >= kSparseThreads ? kSparseThreads : ((max_d + 63) / 64) * 64;
     int rpt = (max_d + threads - 1) / threads;
     if (rpt == 3) rpt = 4;
@@ -83,10 +123,24 @@ int launch_sparse(const RunArgs& a, const DevSystem& s0, int max_d, int prec, in
     QTM_SPARSE_CASE(4, 1) QTM_SPARSE_CASE(4, 2) QTM_SPARSE_CASE(8, 1)
 #undef QTM_SPARSE_CASE
     if (!fn) return -1;
-    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) return -3;
+    // the sliced ELL joins the LDS when it fits there (16-bit columns) and the block
+    // count per CU stays what the registers and the staging allow
+    int lds_max = 0;
+    if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return -3;
+    const int nsl = (max_d + 63) / 64;
+    const size_t ell = (((size_t)max_ell * (prec == 0 ? 16 : 8) + 15) & ~(size_t)15) + (((size_t)max_ell * 2 + 15) & ~(size_t)15) +
+                       (size_t)(2 * nsl + 1) * sizeof(int);
     int nb = 1;
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) return -3;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, threads, lds) != hipSuccess) nb = 1;
     if (nb < 1) nb = 1;
+    a.ell_lds = 0;
+    if (max_d <= 65536 && max_ell > 0 && lds + ell <= (size_t)lds_max) {
+        int nb2 = 0;
+        if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(lds + ell)) != hipSuccess) return -3;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb2, fn, threads, lds + ell) != hipSuccess) nb2 = 0;
+        if (nb2 >= nb) { a.ell_lds = 1; lds += ell; }
+    }
     long long need = ((s0.count + cols - 1) / cols) * (a.n_sys > 0 ? a.n_sys : 1);
     long long blocks = a.persistent ? (long long)ncu * nb : need;
     if (blocks > need) blocks = need;
