@@ -7,6 +7,7 @@
 namespace qtm {
 
 constexpr int kSparseThreads = 256;
+static_assert(sizeof(DevSystem) % 8 == 0, "the descriptor is copied to LDS in 8-byte words");
 
 // One launch can serve several systems (a batch of mixed dimension): a block
 // takes the first system whose trajectory queue is not exhausted, runs it with

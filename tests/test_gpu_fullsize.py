@@ -63,6 +63,28 @@ def test_tfim_full_plain_fp64_sampled():
     _check_sampled(ctx, s, n, 0, np.linspace(0, n - 1, 12).astype(int))
 
 
+def test_tfim_full_batched_fp32_lds_ell():
+    """The benchmarked Ising configuration (batched, FP32 products): the sliced ELL
+    (123 KB) is resident in LDS.  Averages over all 20,000 trajectories against the
+    FP64 run of the same trajectories (ELL read from global memory, checked against
+    the oracle above) within 4.5 sigma/sqrt(N) + 1e-6."""
+    s = w.tfim()
+    n = 20_000
+    print(f"[gpu] tfim full size batched FP32 n={n}", flush=True)
+    ctx = qtm.create_system(s, qtm.Opts(precision=qtm.PREC_FP32, form=qtm.FORM_BATCHED))
+    ctx.run(n, 4)
+    st = ctx.stats()
+    assert st["lds_bytes"] > 120_000, st["lds_bytes"]      # staging + resident ELL
+    mean32, _ = ctx.expect()
+    ref = qtm.create_system(s, qtm.Opts())
+    ref.run(n, 4)
+    mean64, var64 = ref.expect()
+    bound = 4.5 * np.sqrt(np.maximum(var64, 1e-30) / n) + 1e-6
+    dev = np.abs(mean32.real - mean64.real)
+    print("worst deviation / bound", float(np.max(dev / bound)))
+    assert np.all(dev <= bound)
+
+
 def test_hetero_full_batched_fp64_sampled():
     """64 systems x 500 trajectories in the batched tile-class launches, FP64
     products: sampled trajectories of 16 systems recomputed by the oracle."""
