@@ -367,7 +367,9 @@ int setup_system(SysHost& S, const qtm_system& in, int idx, const qtm_opts& o, b
         for (int s = 0; s < nsl; ++s) {
             int w = 0;
             for (int i = 64 * s; i < std::min(d, 64 * s + 64); ++i) w = std::max(w, M.rp[i + 1] - M.rp[i]);
-            wd[s] = (w + 3) & ~3;         // the kernel takes entries in groups of four
+            // the kernel takes entries in groups of four, and may read the first group of
+            // any slice (with zeroed values): every slice holds at least one group
+            wd[s] = std::max(4, (w + 3) & ~3);
             off[s + 1] = off[s] + 64 * wd[s];
         }
         std::vector<int> col(off[nsl], 0);

@@ -87,6 +87,37 @@ def test_sparse_fp32_products_statistical():
     assert ok, worst
 
 
+def _embed(s, d):
+    """The system s in a space of dimension d > s.dim: the extra rows and columns of
+    every operator are empty, so the sliced ELL has slices without entries."""
+    def csr(op):
+        m = op.to_dense()
+        r, c = np.nonzero(m)
+        return w.csr_from_triplets(d, r, c, m[r, c])
+    psi0 = np.zeros(d, dtype=np.complex128)
+    psi0[:s.dim] = s.psi0
+    e_ops = [w.diag(np.concatenate([np.asarray(e.to_dense().diagonal()), np.zeros(d - s.dim)])) for e in s.e_ops]
+    return w.System(s.name + "_embedded", csr(s.H), [csr(c) for c in s.c_ops], psi0, s.tlist, e_ops)
+
+
+def test_sparse_empty_slices():
+    """Ising chain L = 6 embedded in d = 320 (rows 64..319 empty; two rows per
+    thread): FP64 exact against the oracle, FP32 (two-row groups, ELL in LDS)
+    statistical."""
+    s = _embed(w.tfim(L=6, t_end=3.0, n_t=16), 320)
+    n = 64
+    ctx = _gpu(s, n, seed=5)
+    r = oracle.run(s, n, seed=5, jcap=32)
+    print("embedded tfim fp64:", _exact(ctx, r, n))
+    n32 = 1000
+    ctx32 = _gpu(s, n32, seed=6, precision=qtm.PREC_FP32, form=qtm.FORM_BATCHED)
+    mean, var = ctx32.expect()
+    r32 = oracle.run(s, n32, seed=6)
+    ok, worst = _stat(mean.real, r32["var"], r32["mean"].real, n32)
+    print("embedded tfim fp32 worst deviation / bound:", worst)
+    assert ok, worst
+
+
 # ------------------------------------------------------------------ mixed precision (dense)
 def test_dense_fp32_products_statistical_and_close():
     s = w.jaynes_cummings(t_end=10.0, n_t=101)
