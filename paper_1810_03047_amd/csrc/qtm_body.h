@@ -139,6 +139,7 @@ struct Col {
 typedef double gd2_t __attribute__((ext_vector_type(2)));
 typedef float gf2_t __attribute__((ext_vector_type(2)));
 QTM_DI int gload(const int* p, int i) { return ((const __attribute__((address_space(1))) int*)p)[i]; }
+QTM_DI double gload(const double* p, int i) { return ((const __attribute__((address_space(1))) double*)p)[i]; }
 QTM_DI double2 gload(const double2* p, int i) {
     const gd2_t v = ((const __attribute__((address_space(1))) gd2_t*)p)[i];
     return make_double2(v.x, v.y);
@@ -194,6 +195,10 @@ template <int T, int PREC> struct DenseLayout {
     }
     QTM_DI int comp(int e) const { int q = qraw(e); return q < d ? q : -1; }
     QTM_DI int slot(int) const { return 0; }
+    // distinct rows of a lane (each element its own row)
+    static constexpr int NRW = NE;
+    QTM_DI int row_q(int r) const { return comp(r); }
+    static constexpr int erow(int e) { return e; }
     QTM_DI int gcol(int) const { return active ? ct * 16 + c16 : -1; }
 
     // K = M W for every column of the block.
@@ -286,6 +291,10 @@ template <int RPT, int NBC, int PREC> struct SparseLayout {
 
     QTM_DI int comp(int e) const { int q = tid + (e / NBC) * nthr; return q < d ? q : -1; }
     QTM_DI int slot(int e) const { return e % NBC; }
+    // distinct rows of a thread: element e is row e / NBC of column e % NBC
+    static constexpr int NRW = RPT;
+    QTM_DI int row_q(int r) const { return comp(r * NBC); }
+    static constexpr int erow(int e) { return e / NBC; }
     QTM_DI int gcol(int s) const { return s; }
 
     // NR rows (r0 .. r0+NR-1 of this thread) of K = M W over the block's NBC columns.
@@ -355,7 +364,8 @@ template <int RPT, int NBC, int PREC> struct SparseLayout {
             }
         }
         __syncthreads();
-        constexpr int NR = (PREC == 1 && RPT >= 2) ? 2 : 1;   // FP64: register room for one row only
+        // FP32 products: up to four of a thread's rows side by side; FP64: one (register room)
+        constexpr int NR = (PREC == 1 && RPT >= 2) ? (RPT >= 4 ? 4 : RPT) : 1;
 #pragma unroll
         for (int r = 0; r < RPT; r += NR) {
             vt_t acc[NR][NBC];
@@ -537,9 +547,11 @@ struct Body {
 
     // All observables diagonal: |u_q|^2 of every element is formed once per round
     // (a2, zero for columns without an output) and feeds the norm and each of the
-    // group's G observables; one block reduction of 1 + 2G values per group.
-    template <int G> QTM_DI void output_group_diag(int e0, const double (&a2)[L::NE]) {
-        constexpr int NV = 1 + 2 * G;
+    // group's G observables.  The group's diagonal values are loaded once per distinct
+    // row of the thread, all before any is used; REAL (every observable real): the
+    // real parts only.  One block reduction of 1 + G (REAL) or 1 + 2G values.
+    template <int G, bool REAL> QTM_DI void output_group_diag(int e0, const double (&a2)[L::NE]) {
+        constexpr int NV = REAL ? 1 + G : 1 + 2 * G;
         double p[L::CPT][NV];
 #pragma unroll
         for (int b = 0; b < L::CPT; ++b)
@@ -547,32 +559,32 @@ struct Body {
             for (int v = 0; v < NV; ++v) p[b][v] = 0.0;
 #pragma unroll
         for (int e = 0; e < L::NE; ++e) p[Ly.slot(e)][0] += a2[e];
-        // the values of observable g + 1 are loaded while g accumulates (indices
-        // clamped to the last observable, so every load is in range)
         const int last = S.n_e - 1;
-        double2 cur[L::NE], nxt[L::NE];
-        {
-            const double2* dv = S.e_val + S.e_doff[e0 < last ? e0 : last];
+        typedef typename std::conditional<REAL, double, double2>::type ov_t;
+        ov_t v[G][L::NRW];
 #pragma unroll
-            for (int e = 0; e < L::NE; ++e) { const int q = Ly.comp(e); cur[e] = gload(dv, q >= 0 ? q : 0); }
+        for (int g = 0; g < G; ++g) {
+            const int o = e0 + g < last ? e0 + g : last;        // clamped: every load in range
+            const double2* dv = S.e_val + S.e_doff[o];
+#pragma unroll
+            for (int r = 0; r < L::NRW; ++r) {
+                const int q = Ly.row_q(r);
+                if constexpr (REAL) v[g][r] = gload((const double*)dv, 2 * (q >= 0 ? q : 0));
+                else v[g][r] = gload(dv, q >= 0 ? q : 0);
+            }
         }
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-            if (g + 1 < G) {
-                const int on = e0 + g + 1;
-                const double2* dv = S.e_val + S.e_doff[on < last ? on : last];
+            if (e0 + g > last) break;
 #pragma unroll
-                for (int e = 0; e < L::NE; ++e) { const int q = Ly.comp(e); nxt[e] = gload(dv, q >= 0 ? q : 0); }
-            }
-            if (e0 + g <= last) {
-#pragma unroll
-                for (int e = 0; e < L::NE; ++e) {
-                    p[Ly.slot(e)][1 + 2 * g] += cur[e].x * a2[e];
-                    p[Ly.slot(e)][2 + 2 * g] += cur[e].y * a2[e];
+            for (int e = 0; e < L::NE; ++e) {
+                const ov_t x = v[g][L::erow(e)];
+                if constexpr (REAL) p[Ly.slot(e)][1 + g] += x * a2[e];
+                else {
+                    p[Ly.slot(e)][1 + 2 * g] += x.x * a2[e];
+                    p[Ly.slot(e)][2 + 2 * g] += x.y * a2[e];
                 }
             }
-#pragma unroll
-            for (int e = 0; e < L::NE; ++e) cur[e] = nxt[e];
         }
         Ly.template reduce<NV>(p);
         const int tid = threadIdx.x;
@@ -581,8 +593,8 @@ struct Body {
             if (c.omode) {
                 const double nn = Ly.red_sum(tid, 0);
                 for (int g = 0; g < G && e0 + g < S.n_e; ++g) {
-                    const double re = Ly.red_sum(tid, 1 + 2 * g) / nn;
-                    const double im = Ly.red_sum(tid, 2 + 2 * g) / nn;
+                    const double re = Ly.red_sum(tid, REAL ? 1 + g : 1 + 2 * g) / nn;
+                    const double im = REAL ? 0.0 : Ly.red_sum(tid, 2 + 2 * g) / nn;
                     S.X[((size_t)c.traj * S.n_e + e0 + g) * S.n_t + c.kk] = make_double2(re, im);
                 }
             }
@@ -604,10 +616,15 @@ struct Body {
                     if (c.omode) a2[e] = cabs2(vec_mode(e, c));
                 }
             }
-            // groups of up to 7 observables (15 reduced values)
+            bool real = true;
+            for (int o = 0; o < S.n_e; ++o) real = real && S.e_nv[o] == 1;
             for (int e0 = 0; e0 < S.n_e;) {
-                if (S.n_e - e0 <= 3) { output_group_diag<3>(e0, a2); e0 += 3; }
-                else { output_group_diag<7>(e0, a2); e0 += 7; }
+                if (real) {
+                    if (S.n_e - e0 <= 3) { output_group_diag<3, true>(e0, a2); e0 += 3; }
+                    else { output_group_diag<7, true>(e0, a2); e0 += 7; }
+                } else {
+                    output_group_diag<3, false>(e0, a2); e0 += 3;
+                }
             }
             return;
         }
