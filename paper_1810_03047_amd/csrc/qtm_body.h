@@ -479,7 +479,8 @@ struct Body {
     // Products with CSR operators (collapse or observable) on a staged vector.
     QTM_DI double2 csr_row(const int* rp, const int* ci, const double2* val, int q, int gc) const {
         double2 s = make_double2(0.0, 0.0);
-        for (int p = rp[q]; p < rp[q + 1]; ++p) s = cadd(s, cmul(val[p], Ly.Stage[ci[p] * Ly.NB + gc]));
+        const int p1 = gload(rp, q + 1);
+        for (int p = gload(rp, q); p < p1; ++p) s = cadd(s, cmul(gload(val, p), Ly.Stage[gload(ci, p) * Ly.NB + gc]));
         return s;
     }
 
@@ -519,7 +520,7 @@ struct Body {
                 int o = e0 + g;
                 if (o >= S.n_e) break;
                 if (S.e_fmt[o] == 2) {
-                    double2 dv = S.e_val[S.e_doff[o] + q];
+                    double2 dv = gload(S.e_val, S.e_doff[o] + q);
                     p[Ly.slot(e)][1 + 2 * g] += dv.x * a2;
                     p[Ly.slot(e)][2 + 2 * g] += dv.y * a2;
                 } else {
@@ -628,7 +629,7 @@ struct Body {
             }
             return;
         }
-        stage_mode();
+        if (S.any_csr_e) stage_mode();
         for (int e0 = 0; e0 < S.n_e;) {
             if (S.n_e - e0 <= 2 || L::GMAX == 2) { output_group<2>(e0); e0 += 2; }
             else { output_group<(L::GMAX > 2 ? L::GMAX : 2)>(e0); e0 += L::GMAX; }
