@@ -75,7 +75,8 @@ struct Team {
     double* Xb;              // LDS: team reduction exchange [NWT][16][kXV]
     unsigned long long* Ib;  // LDS: trajectory hand-out [16]
     int* Fb;                 // LDS: team flags [4]
-    const double2* Od;       // LDS copy of the diagonal observables [n_e][d] (when od_lds)
+    const double2* Od;       // LDS copy of the diagonal observables [n_e][d] (when od_lds;
+                             // od_lds == 2: every one real)
     const float* Ft;         // LDS: FP32 feature table [d][16] (rows 12, 13: C_n^dag C_n when diagonal)
     int od_lds;
     int lane, lg, c16, wv, RT, d, dp, q0;
@@ -258,8 +259,40 @@ struct Team {
 
     // ------------------------------------------------------------ outputs
     // <u|O_o|u>/<u|u> for every lane with omode != 0 (one team reduction per observable)
+    // real diagonal observables (od_lds == 2): G observables and the norm per team
+    // reduction, real parts only (the imaginary parts are zero)
+    template <int G> QTM_DI void output_round_real(bool on, int o0) {
+        const int qb = qbase();
+        const int no = S.n_e - o0 < G ? S.n_e - o0 : G;
+        const double2* dv0 = Od + (size_t)o0 * d;
+        double p[G + 1];
+#pragma unroll
+        for (int v = 0; v <= G; ++v) p[v] = 0.0;
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+            const int q = qb + cst(e);
+            const double2 u = (on && q < d) ? vec_mode(e) : make_double2(0.0, 0.0);
+            const double a2 = cabs2(u);
+            const int qi = q < d ? q : 0;
+            p[G] += a2;
+#pragma unroll
+            for (int j = 0; j < G; ++j)
+                if (j < no) p[j] = fma(dv0[(size_t)j * d + qi].x, a2, p[j]);
+        }
+        tsum<G + 1>(p);
+        if (on && lg == 0 && wv == 0) {
+#pragma unroll
+            for (int j = 0; j < G; ++j)
+                if (j < no) S.X[((size_t)traj * S.n_e + o0 + j) * S.n_t + kk] = make_double2(p[j] / p[G], 0.0);
+        }
+    }
+
     QTM_DI void output_round(bool on) {
         if (S.any_csr_e || !od_lds) { output_round_staged(on); return; }   // observables not all in LDS
+        if (od_lds == 2) {
+            for (int o0 = 0; o0 < S.n_e; o0 += 3) output_round_real<3>(on, o0);
+            return;
+        }
         // diagonal observables only: each component of u is evaluated once and goes
         // straight into the norm and the observable sums (no vector kept)
         const int qb = qbase();
@@ -1095,7 +1128,8 @@ __global__ void __launch_bounds__(64 * NWT) traj_team_batch_kernel(RunArgs a, in
         si = cur;
         if (si >= a.n_sys) break;
         const DevSystem& S = a.sys[si];
-        const int od_lds = S.any_csr_e ? 0 : 1;
+        int od_lds = S.any_csr_e ? 0 : 2;
+        for (int o = 0; o < S.n_e && od_lds; ++o) if (S.e_nv[o] != 1) od_lds = 1;
         double2* Odl = (double2*)(base + L.od);
         if (od_lds)
             for (int o = 0; o < S.n_e; ++o)
@@ -1204,7 +1238,8 @@ int launch_wave(const RunArgs& a, const DevSystem& s0, int prec, int waves_per_t
     int dp = s0.dp, rt = 2 * dp / 16, T, nwt;
     if (team_shape(rt, waves_per_team, &T, &nwt)) return -1;
     // diagonal observables are copied to LDS when every observable is diagonal
-    int od_lds = 1;
+    int od_lds = 2;                              // 2: every observable real as well
+    for (int o = 0; o < s0.n_e; ++o) if (s0.e_nv[o] != 1) od_lds = 1;
     for (int o = 0; o < s0.n_e; ++o) if (s0.e_fmt[o] != 2) od_lds = 0;
     // single-wave teams: up to 4 per block, sharing the operator in LDS; a shape whose
     // block does not fit the 160 KB of LDS gives way to the next shape of the same tile count
