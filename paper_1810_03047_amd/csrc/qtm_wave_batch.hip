@@ -11,7 +11,7 @@ int team_batch_class(int d) {
     return rt <= 8 ? 0 : rt <= 16 ? 1 : rt <= 32 ? 2 : -1;
 }
 // class 2 (eight row tiles per wave) spills part of its state, and still runs the
-// d <= 256 systems faster than the SpMM kernel (C4: 0.75 -> 0.49 s with FP32 products)
+// d <= 256 systems faster than the SpMM kernel (C4 with FP32 products: 0.49 s against 0.62 s)
 
 int launch_team_batch(const RunArgs& a, int max_d, int max_ne, int prec, hipStream_t st, LaunchInfo* info) {
     const int cls = team_batch_class(max_d);
