@@ -789,13 +789,24 @@ struct Team {
         const double tend = S.tend;
         double p[2] = {0.0, 0.0};
         if (state == ST_STEP) {
+            // FP32 products: the error terms in FP32 too (hardware square root and
+            // reciprocal); the error ratio only steers the step size
+            const float hf = (float)h, atf = (float)A.atol, rtf = (float)A.rtol;
 #pragma unroll
             for (int e = 0; e < NE; ++e) {
                 int q = comp(e);
                 if (q < 0) continue;
-                double2 er = cscale(h, cfma(dp_e(6), to_d2(k[6][e]), to_d2(es[e])));
-                double sc = A.atol + A.rtol * sqrt(fmax(cabs2(y[e]), cabs2(yn[e])));   // = max(|y|, |y_new|): one root
-                p[0] += cabs2(er) / (sc * sc);
+                if constexpr (PREC == 1) {
+                    const float2 k6 = (const float2&)k[6][e], s6 = (const float2&)es[e];
+                    const float erx = hf * fmaf((float)dp_e(6), k6.x, s6.x);
+                    const float ery = hf * fmaf((float)dp_e(6), k6.y, s6.y);
+                    const float scf = fmaf(rtf, __builtin_amdgcn_sqrtf((float)fmax(cabs2(y[e]), cabs2(yn[e]))), atf);
+                    p[0] += (double)((erx * erx + ery * ery) * __builtin_amdgcn_rcpf(fmaxf(scf * scf, 1.17549435e-38f)));
+                } else {
+                    double2 er = cscale(h, cfma(dp_e(6), to_d2(k[6][e]), to_d2(es[e])));
+                    double sc = A.atol + A.rtol * sqrt(fmax(cabs2(y[e]), cabs2(yn[e])));   // = max(|y|, |y_new|): one root
+                    p[0] += cabs2(er) / (sc * sc);
+                }
                 p[1] += cabs2(yn[e]);
             }
         }
