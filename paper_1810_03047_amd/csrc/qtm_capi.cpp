@@ -197,6 +197,18 @@ std::vector<T> build_frag_team(const HCsr& M, int dp, int prec) {
     return f;
 }
 
+// 1 when every tile (rt, s) of the team layout holding a nonzero lies within one tile
+// of the diagonal (a banded operator: the kernel then skips the other tiles' products)
+int team_tile_band(const std::vector<double>& f, int RT) {
+    for (int rt = 0; rt < RT; ++rt)
+        for (int s = 0; s < RT; ++s) {
+            if (rt - s <= 1 && s - rt <= 1) continue;
+            for (int k = 0; k < 256; ++k)
+                if (f[((size_t)rt * RT + s) * 256 + k] != 0.0) return 0;
+        }
+    return 1;
+}
+
 struct DevBuf {
     void* p = nullptr;
     size_t n = 0;
@@ -335,7 +347,9 @@ int setup_system(SysHost& S, const qtm_system& in, int idx, const qtm_opts& o, b
         D.dp = dp;
         D.rt = 2 * dp / 16;
         if (S.team) {
-            if ((rc = upload(S, &D.Mfrag, build_frag_team<double>(M, dp, 0)))) return rc;
+            const std::vector<double> f64 = build_frag_team<double>(M, dp, 0);
+            D.tile_band = team_tile_band(f64, 2 * dp / 16);
+            if ((rc = upload(S, &D.Mfrag, f64))) return rc;
             if ((rc = upload(S, &D.Mfrag32, build_frag_team<float>(M, dp, 1)))) return rc;
             D.Mteam = D.Mfrag;
             D.Mteam32 = D.Mfrag32;

@@ -35,6 +35,7 @@ struct DevSystem {
     const float* Mfrag32;      // same, rounded to FP32
     const double* Mteam;       // team-kernel layout [RT][RT][64][4] (every dense system of a batch)
     const float* Mteam32;
+    int tile_band;             // team layout: every 16-row tile (rt, s) holding a nonzero has |rt - s| <= 1
     const int* sl_off;         // sparse: sliced ELL, 64-row slices; entry offset of each slice
     const int* sl_w;           // width of each slice
     const int* sl_col;         // [slice entries], column-major inside a slice

@@ -61,7 +61,7 @@ __device__ __forceinline__ constexpr double dense_coef(int a, int i) {
 
 // LEARN = false compiles out the segment-start features and the proposal network
 // (kernels that never run the learned form or record segments).
-template <int T, int NWT, int PREC, bool LEARN = true>
+template <int T, int NWT, int PREC, bool LEARN = true, int BAND = 0>
 struct Team {
     typedef typename MfmaT<PREC>::in_t in_t;
     typedef typename std::conditional<PREC == 0, double2, float2>::type kv_t;   // stage vectors
@@ -174,22 +174,28 @@ struct Team {
     }
     // K = M W for the team's 16 columns; W in the lane layout of the state.
     // Every lane of the team must take part (uniform call).
+    static constexpr bool in_band(int tt, int s) { return BAND == 0 || (tt - s <= 1 && s - tt <= 1); }
     template <class V> QTM_DI void product(const V (&W)[NE], kv_t (&K)[NE]) {
         typename MfmaT<PREC>::acc_t acc[T];
 #pragma unroll
         for (int tt = 0; tt < T; ++tt) acc[tt] = 0;
         if constexpr (NWT == 1) {
-            // the lane's own tiles are all source tiles (T == RT)
+            // the lane's own tiles are all source tiles (T == RT).  BAND: the operator's
+            // nonzero tiles lie within one tile of the diagonal, and only those are
+            // multiplied (the others would add exact zeros); the tile pattern is fixed at
+            // compile time, so no branch separates the matrix-core instructions
 #pragma unroll
             for (int s = 0; s < T; ++s) {
                 const In4 b = slots(W[2 * s], W[2 * s + 1]);
                 In4 av[T];
 #pragma unroll
-                for (int tt = 0; tt < T; ++tt) av[tt] = *(const In4*)(Mf + ((size_t)(tt * T + s) * 64 + lane) * 4);
+                for (int tt = 0; tt < T; ++tt)
+                    if (in_band(tt, s)) av[tt] = *(const In4*)(Mf + ((size_t)(tt * T + s) * 64 + lane) * 4);
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
 #pragma unroll
-                    for (int tt = 0; tt < T; ++tt) acc[tt] = MfmaT<PREC>::op(av[tt].v[i], b.v[i], acc[tt]);
+                    for (int tt = 0; tt < T; ++tt)
+                        if (in_band(tt, s)) acc[tt] = MfmaT<PREC>::op(av[tt].v[i], b.v[i], acc[tt]);
                 __builtin_amdgcn_sched_barrier(0);     // one source tile of fragments in flight at a time
             }
         } else {
@@ -1045,7 +1051,7 @@ static __host__ __device__ TeamLds team_lds(int dp, int d, int n_e, int prec, in
     return L;
 }
 
-template <int T, int NWT, int PREC>
+template <int T, int NWT, int PREC, int BAND = 0>
 __global__ void __launch_bounds__(NWT == 1 ? 256 : 64 * NWT) traj_team_kernel(RunArgs a, int od_lds, int tpb) {
     typedef typename MfmaT<PREC>::in_t in_t;
     extern __shared__ double smem[];
@@ -1071,7 +1077,7 @@ __global__ void __launch_bounds__(NWT == 1 ? 256 : 64 * NWT) traj_team_kernel(Ru
     __syncthreads();
     const int team = (threadIdx.x >> 6) / NWT;
     char* tb = base + L.w + (size_t)team * L.team;
-    Team<T, NWT, PREC> W(S, a);
+    Team<T, NWT, PREC, true, BAND> W(S, a);
     W.Mf = Ml;
     W.Wb = (in_t*)tb;
     W.St = (double2*)tb;
@@ -1186,6 +1192,7 @@ __global__ void __launch_bounds__(64 * NWT) traj_team_batch_kernel(RunArgs a, in
 // Instances live in per-shape translation units (qtm_wave_t*.hip) so that they
 // compile in parallel; each defines QTM_WAVE_INSTANCES.
 template <int T, int NWT, int PREC> const void* team_fn_inst();
+template <int T, int PREC> const void* team_fn_band_inst();   // single-wave teams, banded operator
 
 // Team shapes (T row tiles per wave, NWT waves per team) compiled for each number
 // of 16-row tiles RT = 2 dp / 16; the first entry of a row is the default.
@@ -1272,6 +1279,8 @@ int launch_wave(const RunArgs& a, const DevSystem& s0, int prec, int waves_per_t
     if (lds == 0) return -2;
     if (nwt == 1 && T != rt) return -1;          // a single-wave team holds every source tile
     const void* fn = team_fn(T, nwt, prec);
+    if (nwt == 1 && s0.tile_band && T == 4) fn = prec == 0 ? team_fn_band_inst<4, 0>() : team_fn_band_inst<4, 1>();
+    if (nwt == 1 && s0.tile_band && T == 5) fn = prec == 0 ? team_fn_band_inst<5, 0>() : team_fn_band_inst<5, 1>();
     if (!fn) return -1;
     TeamLds L;
     L.total = lds;
