@@ -7,7 +7,7 @@ namespace qtm {
 
 template <int T, int PREC>
 __global__ void __launch_bounds__(512) traj_dense_kernel(RunArgs a, int lds_m) {
-    extern __shared__ double smem[];
+    extern __shared__ __attribute__((aligned(16))) double smem[];   // 16-byte base: double2 staging
     __shared__ int flags[8];
     typedef typename MfmaT<PREC>::in_t in_t;
     const DevSystem& S = a.sys[0];

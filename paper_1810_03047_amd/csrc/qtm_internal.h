@@ -35,7 +35,6 @@ struct DevSystem {
     const float* Mfrag32;      // same, rounded to FP32
     const double* Mteam;       // team-kernel layout [RT][RT][64][4] (every dense system of a batch)
     const float* Mteam32;
-    int tile_band;             // team layout: every 16-row tile (rt, s) holding a nonzero has |rt - s| <= 1
     const int* sl_off;         // sparse: sliced ELL, 64-row slices; entry offset of each slice
     const int* sl_w;           // width of each slice
     const int* sl_col;         // [slice entries], column-major inside a slice
@@ -53,6 +52,7 @@ struct DevSystem {
     const double* f_diag;      // [12 + n_c][d]: rows 0..11 diagonal feature operators (learned form),
                                // rows 12 + n: diagonal of C_n^dag C_n when c_isdiag
     int c_isdiag;              // every C_n has at most one entry per row, so C_n^dag C_n is diagonal
+    int tile_band;             // team layout: every 16-row tile (rt, s) holding a nonzero has |rt - s| <= 1
     const double2* psi0;       // [d]
     const double* tlist;       // [n_t]
     double t0, tend;

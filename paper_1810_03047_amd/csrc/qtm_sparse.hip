@@ -15,7 +15,7 @@ static_assert(sizeof(DevSystem) % 8 == 0, "the descriptor is copied to LDS in 8-
 // first system that may still have work, so finished systems are skipped.
 template <int RPT, int NBC, int PREC>
 __global__ void __launch_bounds__(kSparseThreads) traj_sparse_kernel(RunArgs a) {
-    extern __shared__ double smem[];
+    extern __shared__ __attribute__((aligned(16))) double smem[];   // 16-byte base: double2 staging
     __shared__ int flags[8];
     __shared__ int cur;
     __shared__ DevSystem sys_lds;
