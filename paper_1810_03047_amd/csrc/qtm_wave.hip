@@ -237,6 +237,19 @@ struct Team {
     // D = yn - y, B = h k1 - D, R4 = D - h k7 - B, R5 = h sum_j d_j k_j
     QTM_DI double2 dense_at(int e, double tht) const {
         double2 D = csub(yn[e], y[e]);
+        if constexpr (PREC == 1) {
+            // FP32 products: B, R4, R5 and the two inner levels in FP32 (the stage
+            // vectors are FP32); the outer two levels, with y and D, in FP64
+            const float2 k1 = (const float2&)k[0][e], k7 = (const float2&)k[6][e], sd = (const float2&)ds[e];
+            const float hf = (float)h, th = (float)tht, t1 = 1.f - th, d7 = (float)dp_d(6);
+            const float Dx = (float)D.x, Dy = (float)D.y;
+            const float Bx = fmaf(hf, k1.x, -Dx), By = fmaf(hf, k1.y, -Dy);
+            const float R4x = Dx - fmaf(hf, k7.x, Bx), R4y = Dy - fmaf(hf, k7.y, By);
+            const float R5x = hf * fmaf(d7, k7.x, sd.x), R5y = hf * fmaf(d7, k7.y, sd.y);
+            const float ix = fmaf(th, fmaf(t1, R5x, R4x), Bx), iy = fmaf(th, fmaf(t1, R5y, R4y), By);
+            const double t1d = 1.0 - tht;
+            return make_double2(fma(tht, fma(t1d, (double)ix, D.x), y[e].x), fma(tht, fma(t1d, (double)iy, D.y), y[e].y));
+        }
         double2 B = csub(cscale(h, to_d2(k[0][e])), D);
         double2 R4 = csub(csub(D, cscale(h, to_d2(k[6][e]))), B);
         double2 R5 = cscale(h, cfma(dp_d(6), to_d2(k[6][e]), to_d2(ds[e])));
