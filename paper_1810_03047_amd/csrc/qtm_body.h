@@ -458,6 +458,28 @@ struct Body {
 
     QTM_DI double2 dense_at(int e, double th, const Col& c) const {
         double2 D = csub(yn[e], y[e]);
+        if constexpr (sizeof(kv_t) == 8) {
+            // FP32 products: B, R4, R5 and the two inner levels in FP32 (the stage
+            // vectors are FP32); the outer two levels, with y and D, in FP64
+            const float hf = (float)c.h, thf = (float)th, t1f = 1.f - thf;
+            const float Dx = (float)D.x, Dy = (float)D.y;
+            const float2 k1 = (const float2&)k[0][e], k7 = (const float2&)k[6][e];
+            const float Bx = fmaf(hf, k1.x, -Dx), By = fmaf(hf, k1.y, -Dy);
+            const float R4x = Dx - fmaf(hf, k7.x, Bx), R4y = Dy - fmaf(hf, k7.y, By);
+            float R5x = 0.f, R5y = 0.f;
+#pragma unroll
+            for (int j = 0; j < 7; ++j)
+                if (dp_d(j) != 0.0) {
+                    const float2 kj = (const float2&)k[j][e];
+                    R5x = fmaf((float)dp_d(j), kj.x, R5x);
+                    R5y = fmaf((float)dp_d(j), kj.y, R5y);
+                }
+            R5x *= hf;
+            R5y *= hf;
+            const float ix = fmaf(thf, fmaf(t1f, R5x, R4x), Bx), iy = fmaf(thf, fmaf(t1f, R5y, R4y), By);
+            const double t1 = 1.0 - th;
+            return make_double2(fma(th, fma(t1, (double)ix, D.x), y[e].x), fma(th, fma(t1, (double)iy, D.y), y[e].y));
+        }
         double2 B = csub(cscale(c.h, to_d2(k[0][e])), D);
         double2 R4 = csub(csub(D, cscale(c.h, to_d2(k[6][e]))), B);
         double2 R5 = make_double2(0.0, 0.0);
