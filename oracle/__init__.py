@@ -47,7 +47,7 @@ def lib():
         L.qtmref_dopri_step.argtypes = [C.c_int, _dp, _dp, C.c_double, C.c_double, C.c_double,
                                         _dp, _dp, _dp, C.c_int, _dp, _dp]
         L.qtmref_integrate_nojump.argtypes = [C.c_int, _dp, _dp, C.c_double, C.c_double, C.c_double,
-                                              C.c_double, C.c_int, _dp, _ip, _dp, _dp]
+                                              C.c_double, C.c_int, _dp, _ip, _dp, _dp, C.c_double, _ip]
         L.qtmref_run.argtypes = [C.POINTER(_Op), C.POINTER(_Op), C.c_int, _dp, _dp, C.c_int,
                                  C.POINTER(_Op), C.c_int, C.c_double, C.c_double, C.c_int64,
                                  C.c_uint64, C.c_uint64, C.c_int64, C.c_int64, C.c_int,
@@ -132,15 +132,22 @@ def dopri_step(M: np.ndarray, y: np.ndarray, h: float, rtol: float = 1e-6, atol:
 
 
 def integrate_nojump(M: np.ndarray, y0: np.ndarray, t0: float, t_end: float, rtol: float = 1e-6,
-                     atol: float = 1e-8, cap: int = 100000):
+                     atol: float = 1e-8, cap: int = 100000, first_step: float = 0.0,
+                     with_rejections: bool = False):
+    """Jump-free integration of psi' = M psi; returns the accepted times, the end
+    state and the first step (and the number of rejected attempts when asked).
+    ``first_step`` > 0 replaces the starting-step rule."""
     d = M.shape[0]
     ts = np.zeros(cap)
     n = np.zeros(1, dtype=np.int32)
+    nrej = np.zeros(1, dtype=np.int32)
     yend = np.zeros(d, dtype=np.complex128)
     h0 = np.zeros(1)
     lib().qtmref_integrate_nojump(d, _ptr(_cplx(M)), _ptr(_cplx(y0)), t0, t_end, rtol, atol, cap,
-                                  _ptr(ts), _ptr(n, _ip), _ptr(yend.view(np.float64)), _ptr(h0))
-    return ts[:min(cap, int(n[0]))], yend, float(h0[0])
+                                  _ptr(ts), _ptr(n, _ip), _ptr(yend.view(np.float64)), _ptr(h0),
+                                  float(first_step), _ptr(nrej, _ip))
+    out = (ts[:min(cap, int(n[0]))], yend, float(h0[0]))
+    return out + (int(nrej[0]),) if with_rejections else out
 
 
 # ---------------------------------------------------------- trajectories

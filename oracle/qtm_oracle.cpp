@@ -434,9 +434,15 @@ void features(const Problem& P, const cd* y, double r, double t, double* f, std:
 }
 
 double snap_step(double log_h) {
-    // h = 2^(k/4) with k = round(4 log2 h), evaluated exactly as 2^floor(k/4) * 2^((k mod 4)/4)
+    // h = 2^(k/4) with k = round(4 log2 h), evaluated exactly as 2^floor(k/4) * 2^((k mod 4)/4).
+    // log2 h is first limited to [-40, 10], a non-finite proposal taking the lower end, so
+    // that the proposed step is positive and finite whatever the network returns (the
+    // controller then corrects it like any other first step).
     const double quarter[4] = {1.0, 1.18920711500272106672, 1.41421356237309504880, 1.68179283050742908606};
-    long k = std::lrint(4.0 * (log_h / std::log(2.0)));
+    double l2 = log_h / std::log(2.0);
+    if (!(l2 >= -40.0)) l2 = -40.0;
+    if (l2 > 10.0) l2 = 10.0;
+    long k = std::lrint(4.0 * l2);
     long q = k >= 0 ? k / 4 : -((-k + 3) / 4);
     return std::ldexp(quarter[k - 4 * q], (int)q);
 }
@@ -647,10 +653,12 @@ int qtmref_dopri_step(int d, const double* Mri, const double* yri, double h, dou
 }
 
 /* Integrates d psi/dt = M psi from t0 to tend without jumps and logs the
- * accepted times (for the cross-check of the stepper and controller). */
+ * accepted times (for the cross-check of the stepper and controller).
+ * first_step > 0 replaces the starting-step rule (so that a test can force
+ * rejected attempts); *n_rej receives the number of rejected attempts. */
 int qtmref_integrate_nojump(int d, const double* Mri, const double* yri, double t0, double tend,
                             double rtol, double atol, int cap, double* t_out, int* n_out, double* y_end,
-                            double* h_first) {
+                            double* h_first, double first_step, int* n_rej) {
     Op M;
     M.fmt = 0; M.dim = d; M.v.resize((size_t)d * d);
     for (size_t i = 0; i < M.v.size(); ++i) M.v[i] = cd(Mri[2 * i], Mri[2 * i + 1]);
@@ -659,10 +667,10 @@ int qtmref_integrate_nojump(int d, const double* Mri, const double* yri, double 
     std::vector<std::vector<cd>> k(7, std::vector<cd>(d));
     apply(M, y.data(), k[0].data());
     int64_t rhs = 0;
-    double h = initial_step(M, d, y.data(), k[0].data(), tend - t0, rtol, atol, tmp, f1, rhs);
+    double h = first_step > 0.0 ? first_step : initial_step(M, d, y.data(), k[0].data(), tend - t0, rtol, atol, tmp, f1, rhs);
     *h_first = h;
     double t = t0;
-    int n = 0;
+    int n = 0, nrej = 0;
     bool rejected = false;
     int64_t guard = 0;
     while (t < tend && guard++ < 10000000) {
@@ -673,6 +681,7 @@ int qtmref_integrate_nojump(int d, const double* Mri, const double* yri, double 
         if (!(err <= 1.0)) {
             h *= std::isfinite(err) ? std::max(0.2, 0.9 * std::pow(err, -0.2)) : 0.2;
             rejected = true;
+            ++nrej;
             continue;
         }
         double fac = (err == 0.0) ? 10.0 : std::min(10.0, 0.9 * std::pow(err, -0.2));
@@ -686,6 +695,7 @@ int qtmref_integrate_nojump(int d, const double* Mri, const double* yri, double 
         rejected = false;
     }
     *n_out = n;
+    if (n_rej) *n_rej = nrej;
     for (int i = 0; i < d; ++i) { y_end[2 * i] = y[i].real(); y_end[2 * i + 1] = y[i].imag(); }
     return 0;
 }

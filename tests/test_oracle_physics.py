@@ -10,7 +10,7 @@ from oracle import closed_forms as cf
 from oracle import lindblad
 
 
-def _within(mean, var, ref, n, k=4.5, floor=1e-6):
+def _within(mean, var, ref, n, k=3.0, floor=1e-6):
     """|mean - ref| <= k sigma/sqrt(n) + floor at every point."""
     bound = k * np.sqrt(var / n) + floor
     return np.all(np.abs(mean - ref) <= bound), np.max(np.abs(mean - ref) / bound)

@@ -279,3 +279,111 @@ def test_failure_path_max_steps():
     res = oracle.run(s, 5, seed=0, traj_begin=7, max_steps=3)
     assert res["status"] == -4
     assert res["fail_traj"] == 7
+
+
+# ------------------------------------------------- rejection branch vs scipy
+@pytest.mark.parametrize("make,scale", [(lambda: w.jaynes_cummings(N=10, t_end=5.0), 40.0),
+                                        (lambda: w.two_level(), 60.0),
+                                        (lambda: w.photon_birth_death(), 30.0)])
+def test_rejection_branch_matches_scipy_rk45(make, scale):
+    """A first step far above the starting-step rule's forces rejected attempts.
+    scipy's RK45 (same pair, same standard controller: shrink by
+    max(0.2, 0.9 err^-1/5) on rejection, no growth on the step after a rejection)
+    given the same first step takes the same accepted times and the same number of
+    rejections.  scipy's attempts are counted from its right-hand-side evaluations:
+    one for f(t0), then six per attempted step (FSAL)."""
+    s = make()
+    M = oracle.build_M(s.H, s.c_ops)
+    t0, t1 = s.tlist[0], s.tlist[-1]
+    _, _, h_rule = oracle.integrate_nojump(M, s.psi0, t0, t1, 1e-6, 1e-8)
+    h_first = min(scale * h_rule, 0.5 * (t1 - t0))
+    ts, yend, h0, nrej = oracle.integrate_nojump(M, s.psi0, t0, t1, 1e-6, 1e-8, first_step=h_first,
+                                                 with_rejections=True)
+    assert h0 == h_first
+    solver = RK45(lambda t, y: M @ y, t0, s.psi0.astype(np.complex128), t1, rtol=1e-6, atol=1e-8,
+                  first_step=h_first)
+    ref = []
+    while solver.status == "running":
+        solver.step()
+        ref.append(solver.t)
+    attempts = (solver.nfev - 1) // 6
+    assert (solver.nfev - 1) % 6 == 0
+    scipy_rej = attempts - len(ref)
+    print(f"accepted {len(ref)}, rejected {scipy_rej} (oracle {nrej})")
+    assert scipy_rej >= 1                      # the rejection branch is exercised
+    assert nrej == scipy_rej
+    assert len(ts) == len(ref)
+    assert np.max(np.abs(ts - np.array(ref))) < 1e-9
+    assert np.allclose(yend, solver.y, rtol=0, atol=1e-10)
+
+
+# --------------------------------------------- segment-start features at t0
+def test_features_at_t0_closed_form():
+    """The learned form's 16 segment-start features of the first segment, for the
+    Jaynes-Cummings workload: the atom starts excited (population 1); the cavity
+    populations are the truncated, renormalised Poisson weights of the coherent
+    state, e^-|a|^2 |a|^2n / n!; <C_1^dag C_1> = kappa <n>; <C_2^dag C_2> = gamma_a
+    (excited atom); log r of the segment's Philox threshold; elapsed fraction 0."""
+    from math import factorial
+    N, alpha, kappa, gamma_a = 20, 2.0, 0.1, 0.05
+    s = w.jaynes_cummings(N=N, alpha=alpha, kappa=kappa, gamma_a=gamma_a, t_end=2.0, n_t=21)
+    d = s.dim
+    f_ops = [w.diag(np.tile([0.0, 1.0], N))]
+    for n in range(11):
+        v = np.zeros(d)
+        v[2 * n:2 * n + 2] = 1.0
+        f_ops.append(w.diag(v))
+    res = oracle.run(s, 5, seed=4, f_ops=f_ops, seg_cap=2)
+    p = np.array([np.exp(-alpha ** 2) * alpha ** (2 * n) / factorial(n) for n in range(N)])
+    p /= p.sum()
+    n_mean = float(np.sum(np.arange(N) * p))
+    for i in range(5):
+        f = res["segs"][i, 0, :16]
+        r, _ = _uniforms(i, 1, seed=4)
+        ref = np.concatenate([[1.0], p[:11], [kappa * n_mean, gamma_a, np.log(r[0]), 0.0]])
+        assert np.max(np.abs(f - ref)) < 1e-12, (i, f - ref)
+        assert res["segs"][i, 0, 19] == 1.0
+
+
+# ------------------------------------------------------ step-size underflow
+def test_failure_path_step_underflow():
+    """H = 1e12 sigma_x on [1e6, 1e6 + 1]: the accepted steps grow until the first
+    rejection, whose reduced step lies below 16 eps |t| (the analogue of the
+    paper's solver reporting an error level): the trajectory fails with -4, long
+    before max_steps, after exactly one rejection."""
+    s = w.two_level()
+    s.H = w.dense(1e12 * w.systems.SX)
+    s.tlist = np.array([1e6, 1e6 + 1.0])
+    res = oracle.run(s, 3, seed=0, traj_begin=5, max_steps=1_000_000)
+    assert res["status"] == -4
+    assert res["fail_traj"] == 5
+    acc, rej = res["stats"][0, 0], res["stats"][0, 1]
+    assert rej == 1 and 0 < acc < 100, (acc, rej)
+
+
+# -------------------------------------------------- proposal step limits
+def test_snap_limits_extreme_proposals():
+    """The snapped proposal is 2^(k/4) with log2 h limited to [-40, 10]; a
+    non-finite proposal takes the lower end."""
+    assert oracle.snap_step(-1e4) == 2.0 ** -40
+    assert oracle.snap_step(1e30) == 2.0 ** 10
+    assert oracle.snap_step(float("nan")) == 2.0 ** -40
+    assert oracle.snap_step(float("-inf")) == 2.0 ** -40
+    assert oracle.snap_step(float("inf")) == 2.0 ** 10
+    assert oracle.snap_step(np.log(2.0) * -40.0) == 2.0 ** -40
+
+
+def test_learned_run_with_out_of_range_proposal_completes():
+    """A proposal network whose output bias is -1e4 (h = e^-10000) would otherwise
+    give h = 0 and spend max_steps attempts; with the limit the controller grows the
+    first step from 2^-40 and every trajectory completes with ordinary step counts."""
+    s = w.two_level()
+    p = np.zeros(oracle.mlp_ntotal())
+    p[-16:] = 1.0
+    nparam = oracle.mlp_nparam()
+    p[nparam - 3] = -1e4
+    res = oracle.run(s, 16, seed=2, mlp=p, max_steps=5000)
+    assert res["status"] == 0
+    plain = oracle.run(s, 16, seed=2)
+    assert np.array_equal(res["jump_counts"], plain["jump_counts"])
+    assert res["stats"][:, 0].max() < 3 * plain["stats"][:, 0].max()
