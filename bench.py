@@ -40,6 +40,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "trajectories/sec to t_end at rtol 1e-6; learned+batched form vs plain"
 PEAK = {"fp64": 78.6, "fp32": 157.3}          # TFLOP/s, MI355X dense matrix peaks
+# FP32 vector arithmetic without packed (two-wide) FP32 instructions, which this code is
+# built without: 256 CUs x 4 SIMDs x 16 FMA lanes per clock x 2 flops x 2.4 GHz
+PEAK_FP32_VALU = 256 * 4 * 16 * 2 * 2.4e9 / 1e12       # 78.6 TFLOP/s
 NTRAJ = 10_000
 
 
@@ -109,7 +112,12 @@ def _neutral_params(qtm):
     return p
 
 
-def training_data(qtm, system, n_traj_data: int = 170_000, seed: int = 1):
+# Training trajectories use their own seed, disjoint from every timed seed (0 .. K-1)
+# and warm-up seed (1000 + i), so the learned form is never timed on its training data.
+TRAIN_SEED = 1_000_003
+
+
+def training_data(qtm, system, n_traj_data: int = 170_000, seed: int = TRAIN_SEED):
     """Segment records of the plain FP64 GPU solver -> (features, targets).
 
     Targets: log of the controller's step after the segment's first accepted
@@ -164,20 +172,102 @@ def time_form(qtm, system, opts, steps, warmup, seed0=0, proposal=None):
                 rej=rej / steps, segments=seg / steps, launch=info)
 
 
-def cpu_baseline(system, target_s: float = 12.0):
-    """The FP64 oracle on the host cores over a bounded sample of the workload."""
+def _threads():
+    """Host threads for the oracle: the CPU share of this process (at most 16, the share a
+    one-GPU machine grants a job), with nproc recorded beside it."""
+    try:
+        share = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        share = os.cpu_count() or 1
+    return min(16, share), os.cpu_count() or 1, share
+
+
+def cpu_baseline(system, mlp=None, f_ops=None, cpu_s: float = 20.0):
+    """The FP64 oracle on the host cores over a bounded sample of the workload (the
+    headline form: with the proposal weights the GPU uses when ``mlp`` is given).
+    Both builds of the oracle are timed (the parity build and the -O3 AVX2/FMA build)
+    on all the threads this process may use, and the faster one single-threaded."""
     import oracle
-    threads = min(16, os.cpu_count() or 1)
+    threads, nproc, share = _threads()
+    kw = dict(mlp=mlp, f_ops=f_ops)
     t0 = time.perf_counter()
-    oracle.run(system, 64, seed=0, nthreads=threads)
+    oracle.run(system, 64, seed=0, nthreads=threads, **kw)
     dt = time.perf_counter() - t0
-    n = int(max(64, min(20000, 64 * target_s / max(dt, 1e-3))))
+    # about cpu_s seconds of CPU work per build at this rate
+    n = int(max(64, min(20000, 64 * cpu_s / max(dt * threads, 1e-3))))
+    rates = {}
+    for name, fast in (("parity_build_O2", False), ("timing_build_O3_avx2", True)):
+        t0 = time.perf_counter()
+        oracle.run(system, n, seed=0, nthreads=threads, fast=fast, **kw)
+        rates[name] = n / (time.perf_counter() - t0)
+    best = max(rates, key=rates.get)
+    fast_best = best == "timing_build_O3_avx2"
+    n1 = max(16, n // threads)
     t0 = time.perf_counter()
-    oracle.run(system, n, seed=0, nthreads=threads)
-    dt = time.perf_counter() - t0
-    return {"value": n / dt, "unit": "trajectories/s", "cores": threads, "kind": "oracle",
-            "sample": f"trajectories 0..{n - 1} of the same workload (seed 0), FP64 C++ oracle, "
-                      f"{threads} OpenMP threads, {dt:.1f} s"}
+    oracle.run(system, n1, seed=0, nthreads=1, fast=fast_best, **kw)
+    single = n1 / (time.perf_counter() - t0)
+    return {"value": rates[best], "unit": "trajectories/s", "cores": threads, "kind": "oracle",
+            "sample": f"trajectories 0..{n - 1} of the same workload (seed 0{', same proposal weights' if mlp is not None else ''}), "
+                      f"FP64 C++ oracle, {threads} OpenMP threads (nproc {nproc}, affinity {share}); "
+                      f"{best} is the faster build",
+            "builds": rates, "nproc": nproc, "single_thread": {"value": single, "build": best, "sample": f"trajectories 0..{n1 - 1}"}}
+
+
+def oracle_check(qtm, system, opts, proposal, ntraj, seed=0, plain_exact=False):
+    """The headline form on trajectories 0..ntraj-1 of one timed seed against the FP64
+    oracle (parity build) on the same trajectories and random streams: the largest
+    deviation of the averages in units of the oracle's sigma/sqrt(N) (the stated bound is
+    3 plus 1e-6/(sigma/sqrt(N))), the fraction of trajectories with the oracle's jump
+    counts, and the largest jump-time difference among trajectories whose jump counts
+    and channels agree."""
+    import dataclasses
+    import oracle
+    o = dataclasses.replace(opts, record_jumps=32, keep_traj=0)
+    ctx = qtm.create_system(system, o)
+    if proposal is not None:
+        ctx.set_proposal(*proposal)
+    ctx.run(ntraj, seed)
+    mean, _ = ctx.expect()
+    jn = np.zeros(ntraj, dtype=np.int64)
+    jt = np.zeros((ntraj, 32))
+    jc = np.zeros((ntraj, 32), dtype=np.int32)
+    for i in range(ntraj):
+        t, c, cnt = ctx.jumps(i)
+        jn[i], jt[i, :len(t)], jc[i, :len(c)] = cnt, t, c
+    ctx.destroy()
+    threads, _, _ = _threads()
+    mlp = None
+    if proposal is not None:
+        mlp = _working_params(proposal[0])
+    r = oracle.run(system, ntraj, seed=seed, nthreads=threads, jcap=32, mlp=mlp,
+                   f_ops=proposal[1] if proposal is not None else None)
+    sig = np.sqrt(np.maximum(r["var"], 0.0) / ntraj)
+    dev = np.abs(mean.real - r["mean"].real)
+    z = dev / np.maximum(sig, 1e-300)
+    bound = 3.0 * sig + 1e-6
+    same = jn == r["jump_counts"]
+    jtd = 0.0
+    for i in np.nonzero(same)[0]:
+        m = int(min(jn[i], 32))
+        if m and np.array_equal(jc[i, :m], r["jump_channels"][i, :m]):
+            jtd = max(jtd, float(np.max(np.abs(jt[i, :m] - r["jump_times"][i, :m]))))
+    return {"ntraj": ntraj, "seed": seed, "max_dev_over_sigma": float(np.max(np.where(sig > 0, z, 0.0))),
+            "max_dev_over_bound": float(np.max(dev / bound)), "max_abs_dev": float(np.max(dev)),
+            "identical_jump_counts": float(np.mean(same)), "max_jump_time_diff": jtd,
+            "within_bound": bool(np.all(dev <= bound))}
+
+
+def _working_params(p32):
+    """The values the device computes with: BF16-rounded weight matrices (round to
+    nearest even), FP32 biases and standardisation, as FP64 for the oracle."""
+    p = np.asarray(p32, dtype=np.float32).copy()
+    nf, nh, no = 16, 64, 3
+    for a, n in ((0, nh * nf), (nh * nf + nh, nh * nh), (nh * nf + nh + nh * nh + nh, no * nh)):
+        u = p[a:a + n].view(np.uint32).copy()
+        u += np.uint32(0x7FFF) + ((u >> 16) & 1)
+        u &= np.uint32(0xFFFF0000)
+        p[a:a + n] = u.view(np.float32)
+    return p.astype(np.float64)
 
 
 def other_workload(a, qtm, w, torch):
@@ -225,7 +315,9 @@ def other_workload(a, qtm, w, torch):
                          tflops=float(np.mean(fl)) / (float(np.mean(kms)) * 1e-3) / 1e12)
         ctx.destroy()
     b = out["best"]
-    peak = PEAK["fp32"]
+    # the sparse kernel is bound by vector ALU work (non-packed FP32); the tile classes by
+    # the FP32 matrix cores
+    peak = PEAK_FP32_VALU if a.workload == "tfim" else PEAK["fp32"]
     line = {
         "metric": METRIC, "value": b["value"], "unit": "trajectories/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": b["ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -292,9 +384,9 @@ def main():
         o.team_waves = tw["team_waves"]
         print(f"[bench] plain: team_waves {tw}", file=sys.stderr, flush=True)
         res["plain"] = time_form(qtm, system, o, a.steps, a.warmup)
-    best_name, train_info = None, None
+        opts_plain = o
+    best_name, train_info, proposal = None, None, None
     if "best" in forms:
-        proposal = None
         form = qtm.FORM_BATCHED
         if not a.no_learned:
             t0 = time.perf_counter()
@@ -352,7 +444,17 @@ def main():
         line["per_traj"] = {k: {"accepted": r["acc"] / NTRAJ, "rejected": r["rej"] / NTRAJ,
                                 "segments": r["segments"] / NTRAJ} for k, r in res.items()}
     if not a.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(system)
+        # the CPU leg: the oracle timed on the host, and the same oracle (parity build)
+        # checking the timed forms on trajectories 0..NTRAJ-1 of timed seed 0
+        line["cpu_baseline"] = cpu_baseline(system, *(
+            (_working_params(proposal[0]), proposal[1]) if ("best" in res and proposal is not None) else (None, None)))
+        print(f"[bench] cpu baseline: {line['cpu_baseline']}", file=sys.stderr, flush=True)
+        checks = {}
+        if "best" in res:
+            checks["headline"] = oracle_check(qtm, system, o, proposal, NTRAJ, seed=0)
+        if "plain" in res:
+            checks["plain"] = oracle_check(qtm, system, opts_plain, None, NTRAJ, seed=0)
+        line["oracle_check"] = checks
     print(json.dumps(line), flush=True)
 
 

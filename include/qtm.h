@@ -109,6 +109,11 @@ typedef struct {
     int32_t blocks, threads, tile_cols, lds_bytes;   /* launch configuration used */
     int64_t max_team_passes;  /* most product passes of one trajectory team (the launch's critical
                                  path; team kernel only, 0 for the others) */
+    int64_t root_evals;       /* evaluations of the dense-output norm polynomial by the jump-time
+                                 root finds (32-point scan plus bisection to 1e-13 in theta) */
+    int32_t team_shape;       /* small dense kernel: 100 x row tiles per wave + waves per team,
+                                 plus 1000 when the banded-operator instance ran; 0 otherwise */
+    int32_t reserved_stats;
 } qtm_stats_t;
 
 /* A system for qtm_create_batch (same meaning as the qtm_create arguments). */
@@ -152,20 +157,32 @@ int qtm_create(qtm_ctx** out, const qtm_op* H, const qtm_op* c_ops, int32_t n_c,
 int qtm_create_batch(qtm_ctx** out, int32_t n_sys, const qtm_system* sys, const qtm_opts* o);
 
 /* Runs trajectories 0..ntraj-1 (of every system of a batch) on the context's
- * stream and waits for them.  Equivalent to qtm_run_range(ctx, 0, ntraj, seed).
+ * stream and waits for them: every trajectory follows Algorithm 1 (steps A-D:
+ * threshold draw, no-jump evolution under H_eff until the norm falls below the
+ * threshold, channel choice by the probabilities P_n, jump and renormalisation)
+ * from t0 to the end time, and its expectation values are averaged over the
+ * trajectories on the device (the final averaging of Sec. 3).  Equivalent to
+ * qtm_run_range(ctx, 0, ntraj, seed).  Outputs stay in device memory owned by
+ * the context until the next run or qtm_destroy.
  * Errors: QTM_E_INVAL (ntraj < 1), QTM_E_NOMEM, QTM_E_DEVICE, QTM_E_STEP (one
- * or more trajectories failed; qtm_stats names the smallest index; averages are
- * then not available). */
+ * or more trajectories failed -- the analogue of the negative solver status the
+ * paper's solver wrapper reports, Sec. 3; qtm_stats names the smallest index;
+ * averages are then not available). */
 int qtm_run(qtm_ctx* ctx, int64_t ntraj, uint64_t seed);
 
-/* Runs trajectories traj_begin .. traj_begin+count-1.  Because the random
+/* Runs trajectories traj_begin .. traj_begin+count-1 (traj_begin >= 0,
+ * count >= 1).  This is the work unit of the paper's master/worker split of
+ * independent trajectories over computing nodes (Sec. 3): because the random
  * stream of trajectory i depends only on (seed, system, i), the sums of
- * disjoint ranges combine into the sums of their union (sharding property). */
+ * disjoint ranges combine into the sums of their union.  Errors as qtm_run. */
 int qtm_run_range(qtm_ctx* ctx, int64_t traj_begin, int64_t count, uint64_t seed);
 
-/* Trajectory averages of the last run (of system 0 for a batch):
+/* Trajectory averages of the last run (of system 0 for a batch): the final
+ * trajectory of Sec. 3, i.e. the mean over trajectories of <psi|O_k|psi>/<psi|psi>
+ * at every output time (Sec. 2.2, expectation values of the unnormalised state).
  *   mean [n_e][n_t] complex (interleaved), var [n_e][n_t] variance of the real
- *   part over trajectories (nullable).  Host buffers, caller-allocated.
+ *   part over trajectories (nullable).  Host buffers, caller-allocated; summed in
+ *   FP64 in trajectory-index order, so independent of scheduling.
  * Errors: QTM_E_STATE before a successful qtm_run. */
 int qtm_expect(const qtm_ctx* ctx, double* mean, double* var);
 
@@ -182,8 +199,12 @@ int qtm_sums(const qtm_ctx* ctx, int32_t s, double* sum, double* sumsq, int64_t*
 int qtm_traj_expect(const qtm_ctx* ctx, int32_t s, double* X);
 
 /* Jump log of trajectory traj (index within the last run's range) of system s
- * (requires record_jumps > 0): up to cap (time, channel) pairs; *count
- * receives the total number of jumps (which may exceed the log capacity). */
+ * (requires record_jumps > 0): the jump times (roots of ||psi(t)||^2 = r,
+ * Algorithm 1 step B) and channels n (step C, Eq. for P_i) in order, up to cap
+ * (time, channel) pairs written to the host buffers times[cap], channels[cap]
+ * (channel -1: every P_n was zero and the state was only renormalised); *count
+ * receives the total number of jumps (which may exceed the log capacity).
+ * Errors: QTM_E_STATE without record_jumps or before a run, QTM_E_INVAL. */
 int qtm_jumps(const qtm_ctx* ctx, int32_t s, int64_t traj, int32_t cap, double* times, int32_t* channels,
               int32_t* count);
 
@@ -191,7 +212,9 @@ int qtm_jumps(const qtm_ctx* ctx, int32_t s, int64_t traj, int32_t cap, double* 
  * rejected steps, segments, jumps (int32), for system s. */
 int qtm_traj_stats(const qtm_ctx* ctx, int32_t s, int32_t* stats);
 
-/* Statistics of the last run. */
+/* Statistics of the last run (the integrator's work per Sec. 2.1's adaptive
+ * step control, and the launch configuration), copied to the host struct *st.
+ * Filled also after a run that failed with QTM_E_STEP. */
 int qtm_stats(const qtm_ctx* ctx, qtm_stats_t* st);
 
 /* ---------------------------------------------------- learned proposal */

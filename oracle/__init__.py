@@ -21,6 +21,7 @@ import numpy as np
 from . import build as _build
 
 _lib = None
+_lib_fast = None
 
 
 class _Op(C.Structure):
@@ -35,10 +36,12 @@ _ip = C.POINTER(C.c_int32)
 _lp = C.POINTER(C.c_int64)
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        path = _build.ensure_built()
+def lib(fast: bool = False):
+    """The parity build, or (fast=True) the -O3 AVX2/FMA build used only to time the
+    oracle as a CPU baseline."""
+    global _lib, _lib_fast
+    if (_lib_fast if fast else _lib) is None:
+        path = _build.ensure_built(fast)
         L = C.CDLL(path)
         L.qtmref_philox4x64_10.argtypes = [C.POINTER(C.c_uint64)] * 3
         L.qtmref_uniform53.argtypes = [C.c_uint64]
@@ -62,8 +65,11 @@ def lib():
         L.qtmref_tableau.argtypes = [_dp] * 5
         L.qtmref_snap_step.argtypes = [C.c_double]
         L.qtmref_snap_step.restype = C.c_double
-        _lib = L
-    return _lib
+        if fast:
+            _lib_fast = L
+        else:
+            _lib = L
+    return _lib_fast if fast else _lib
 
 
 def _ptr(a, t=_dp):
@@ -156,13 +162,15 @@ NF = 16
 
 def run(system, ntraj: int, seed: int = 0, sys_id: int = 0, traj_begin: int = 0,
         rtol: float = 1e-6, atol: float = 1e-8, max_steps: int = 10_000_000, nthreads: int = 0,
-        mlp: Optional[np.ndarray] = None, f_ops=None, jcap: int = 64, seg_cap: int = 0) -> dict:
+        mlp: Optional[np.ndarray] = None, f_ops=None, jcap: int = 64, seg_cap: int = 0,
+        fast: bool = False) -> dict:
     """Runs trajectories [traj_begin, traj_begin + ntraj) of ``system`` in FP64.
 
     Returns per-trajectory outputs ``X`` [ntraj, n_e, n_t] (complex), the
     index-ordered average ``mean`` [n_e, n_t] (complex) and ``var`` (of the
     real part), the jump log, per-trajectory stats (accepted, rejected, rhs,
-    segments, jumps), optional segment records and the status.
+    segments, jumps), optional segment records and the status.  ``fast`` runs the
+    -O3 AVX2/FMA timing build instead of the parity build.
     """
     s = system
     n_e, n_t = len(s.e_ops), len(s.tlist)
@@ -180,7 +188,7 @@ def run(system, ntraj: int, seed: int = 0, sys_id: int = 0, traj_begin: int = 0,
     psi = _cplx(s.psi0)
     tl = np.ascontiguousarray(s.tlist, dtype=np.float64)
     mp = None if mlp is None else np.ascontiguousarray(mlp, dtype=np.float64)
-    st = lib().qtmref_run(harr, carr, len(s.c_ops), _ptr(psi), _ptr(tl), n_t, earr, n_e,
+    st = lib(fast).qtmref_run(harr, carr, len(s.c_ops), _ptr(psi), _ptr(tl), n_t, earr, n_e,
                           rtol, atol, max_steps, seed, sys_id, traj_begin, ntraj, nthreads,
                           _ptr(mp), farr, len(f_ops or []),
                           _ptr(X.view(np.float64)), jcap, _ptr(jt), _ptr(jc, _ip), _ptr(jn, _ip),

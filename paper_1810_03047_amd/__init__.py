@@ -56,7 +56,8 @@ class _Stats(C.Structure):
                 ("jumps", C.c_int64), ("rhs_evals", C.c_int64), ("passes", C.c_int64), ("failed_traj", C.c_int64),
                 ("kernel_ms", C.c_double), ("elapsed_ms", C.c_double), ("blocks", C.c_int32),
                 ("threads", C.c_int32), ("tile_cols", C.c_int32), ("lds_bytes", C.c_int32),
-                ("max_team_passes", C.c_int64)]
+                ("max_team_passes", C.c_int64), ("root_evals", C.c_int64),
+                ("team_shape", C.c_int32), ("reserved_stats", C.c_int32)]
 
 
 class _System(C.Structure):
@@ -111,6 +112,12 @@ def load(path: Optional[str] = None) -> C.CDLL:
     p = path or LIB_PATH
     if not os.path.exists(p):
         raise QtmError(E_DEVICE, f"{p} is missing: run `python -m paper_1810_03047_amd.build`")
+    try:
+        # torch first, so that the library binds to the HIP runtime torch has loaded
+        # (one runtime per process; a second copy loaded later sees no device)
+        import torch  # noqa: F401
+    except ImportError:  # pragma: no cover
+        pass
     L = C.CDLL(p)
     for name, (res, args) in _SIGS.items():
         fn = getattr(L, name)
@@ -189,6 +196,10 @@ class Context:
 
     def __init__(self, handle: C.c_void_p, dims, opts: Opts):
         self._h = handle
+        # the library's destroy entry point is held by the context itself, so that a
+        # context still alive when the interpreter shuts down (module globals already
+        # cleared) is freed all the same
+        self._destroy_fn = load().qtm_destroy
         self.dims = dims            # list of (d, n_e, n_t) per system
         self.opts = opts
         self.last_count = 0
@@ -197,9 +208,11 @@ class Context:
         self.destroy()
 
     def destroy(self):
-        if getattr(self, "_h", None):
-            load().qtm_destroy(self._h)
-            self._h = None
+        h = getattr(self, "_h", None)
+        fn = getattr(self, "_destroy_fn", None)
+        if h and fn is not None:
+            fn(h)
+        self._h = None
 
     # -------------------------------------------------------------- runs
     def run(self, ntraj: int, seed: int = 0):

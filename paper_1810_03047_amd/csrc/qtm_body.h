@@ -93,6 +93,15 @@ __device__ __forceinline__ double exp2_quarter(int k) {
     int q = k >> 2;                                   // floor division
     return ldexp(f[k & 3], q);
 }
+// The learned form's first step from the network's log-step lh: h = 2^(k/4) with
+// k = round(4 log2 h), log2 h first limited to [-40, 10] (a non-finite output takes the
+// lower end) so that the step is positive and finite whatever the network returns
+__device__ __forceinline__ double snap_proposal(float lh) {
+    double l2 = (double)lh / 0.69314718055994530942;
+    if (!(l2 >= -40.0)) l2 = -40.0;
+    if (l2 > 10.0) l2 = 10.0;
+    return exp2_quarter((int)rint(4.0 * l2));
+}
 
 // ------------------------------------------------------------------ complex
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
@@ -449,6 +458,8 @@ struct Body {
     int* flags;
 
     unsigned long long passes = 0;   // product passes of this block (thread 0), added once at exit
+    unsigned long long roots = 0;    // norm-polynomial evaluations of the jump-time root finds of
+                                     // this thread's columns, added once at exit
     // vectors (registers): state and step result in FP64, stage derivatives in the product precision
     typedef typename L::kv_t kv_t;
     double2 y[L::NE], yn[L::NE];
@@ -853,8 +864,7 @@ struct Body {
                     f[15] = (float)((c.t - S.t0) / (S.tend - S.t0));
                     if (A.learned) {
                         float lh = mlp_logh(A.mlp, f);
-                        // snap to the grid 2^(k/4): h = 2^(round(4 log2 h)/4)
-                        double h = exp2_quarter((int)rint(4.0 * ((double)lh / 0.69314718055994530942)));
+                        double h = snap_proposal(lh);
                         c.h = fmin(h, S.tend - c.t);
                         c.state = ST_STEP;
                     }
@@ -1102,10 +1112,12 @@ struct Body {
                 double lo = 0.0, hi = 1.0;
                 for (int m = 1; m <= 32; ++m) {
                     double th = (double)m / 32.0;
+                    ++roots;
                     if (f(th) < 0.0) { hi = th; lo = (double)(m - 1) / 32.0; break; }
                 }
                 while (hi - lo > 1e-13) {
                     double mid = 0.5 * (lo + hi);
+                    ++roots;
                     if (f(mid) < 0.0) hi = mid; else lo = mid;
                 }
                 c.th = 0.5 * (lo + hi);

@@ -700,18 +700,22 @@ int qtm_run(qtm_ctx* ctx, int64_t ntraj, uint64_t seed) { return qtm_run_range(c
 // clearing the outputs and counters (fill kernels, so that the sequence can be
 // captured into a graph), the trajectory kernel(s) between two device timestamps, and the
 // fixed-order averages.
-static int enqueue_run(qtm_ctx* c, const qtm::RunArgs& a, long long count, hipStream_t st, qtm::LaunchInfo* li) {
-    const int segc = c->o.seg_cap;
+// The outputs are the ones the host copies of the system descriptors name (X, counters,
+// segment records, queue); avg, when given, replaces system 0's averaging buffers
+// (partial sums, sums, sums of squares).
+static int enqueue_run(qtm_ctx* c, const qtm::RunArgs& a, long long count, hipStream_t st, qtm::LaunchInfo* li,
+                       double* const* avg = nullptr) {
+    const int segc = a.seg_cap;
     auto fill = [&](void* p, size_t bytes, unsigned long long v) {
         return qtm::launch_fill(p, bytes, v, st) ? fail(QTM_E_DEVICE, "fill kernel launch failed") : QTM_OK;
     };
     int rc;
     for (auto& S : c->sys) {
         size_t m = (size_t)S.n_e * S.n_t;
-        if ((rc = fill(S.queue.p, sizeof(unsigned long long), 0))) return rc;
-        if ((rc = fill(S.X.p, sizeof(double2) * m * count, 0))) return rc;
-        if ((rc = fill(S.tstat.p, sizeof(int) * 4 * count, 0))) return rc;
-        if (segc && (rc = fill(S.segs.p, sizeof(float) * qtm::kSegRec * segc * count, 0))) return rc;
+        if ((rc = fill(S.dev.queue, sizeof(unsigned long long), 0))) return rc;
+        if ((rc = fill(S.dev.X, sizeof(double2) * m * count, 0))) return rc;
+        if ((rc = fill(S.dev.tstat, sizeof(int) * 4 * count, 0))) return rc;
+        if (segc && (rc = fill(S.dev.segs, sizeof(float) * qtm::kSegRec * segc * count, 0))) return rc;
     }
     if ((rc = fill(c->d_fail, sizeof(long long), (unsigned long long)LLONG_MAX))) return rc;
     if ((rc = fill(c->d_counters, 4 * sizeof(unsigned long long), 0))) return rc;
@@ -801,10 +805,39 @@ static int enqueue_run(qtm_ctx* c, const qtm::RunArgs& a, long long count, hipSt
         }
     }
     if (qtm::launch_stamp(c->d_stamp + 1, st)) return fail(QTM_E_DEVICE, "timestamp kernel launch failed");
-    for (auto& S : c->sys)
-        if (qtm::launch_average(S.dev, (double*)S.avg_part.p, (double*)S.sum.p, (double*)S.sumsq.p, st))
-            return fail(QTM_E_DEVICE, "average kernel launch failed");
+    for (size_t si = 0; si < c->sys.size(); ++si) {
+        auto& S = c->sys[si];
+        double* part = (avg && si == 0) ? avg[0] : (double*)S.avg_part.p;
+        double* sum = (avg && si == 0) ? avg[1] : (double*)S.sum.p;
+        double* sumsq = (avg && si == 0) ? avg[2] : (double*)S.sumsq.p;
+        if (qtm::launch_average(S.dev, part, sum, sumsq, st)) return fail(QTM_E_DEVICE, "average kernel launch failed");
+    }
     return QTM_OK;
+}
+
+// Launch arguments of one run of count trajectories.
+static qtm::RunArgs run_args(const qtm_ctx* c, long long count, int jcap, int segc) {
+    qtm::RunArgs a{};
+    a.sys = c->d_sys;
+    a.n_sys = (int)c->sys.size();
+    a.sys_cursor = c->d_cursor;
+    a.rtol = c->o.rtol;
+    a.atol = c->o.atol;
+    a.max_steps = c->o.max_steps;
+    a.jcap = jcap;
+    a.seg_cap = segc;
+    a.learned = (c->o.form & QTM_FORM_LEARNED) ? 1 : 0;
+    a.mlp = c->d_mlp;
+    a.mlpf = c->d_mlpf;
+    a.fail = c->d_fail;
+    a.counters = c->d_counters;
+    a.tile_cols = c->o.tile_cols;
+    a.persistent = (c->o.form & QTM_FORM_BATCHED) ? 1 : 0;
+    // failsafe bound on block cycles: every slot may run all its trajectories at max_steps
+    long long per_slot = count;   // worst case (one slot)
+    long long mc = (c->o.max_steps + 4) * 3;
+    a.max_cycles = (per_slot > 0 && mc < LLONG_MAX / (per_slot + 1)) ? mc * (per_slot + 1) : LLONG_MAX;
+    return a;
 }
 
 int qtm_run_range(qtm_ctx* c, int64_t traj_begin, int64_t count, uint64_t seed) {
@@ -854,26 +887,7 @@ int qtm_run_range(qtm_ctx* c, int64_t traj_begin, int64_t count, uint64_t seed) 
         HIPCHECK(hipMemcpyAsync(c->d_sys_cls, dsc.data(), sizeof(qtm::DevSystem) * dsc.size(), hipMemcpyHostToDevice, c->stream));
     }
 
-    qtm::RunArgs a{};
-    a.sys = c->d_sys;
-    a.n_sys = (int)c->sys.size();
-    a.sys_cursor = c->d_cursor;
-    a.rtol = c->o.rtol;
-    a.atol = c->o.atol;
-    a.max_steps = c->o.max_steps;
-    a.jcap = jcap;
-    a.seg_cap = segc;
-    a.learned = (c->o.form & QTM_FORM_LEARNED) ? 1 : 0;
-    a.mlp = c->d_mlp;
-    a.mlpf = c->d_mlpf;
-    a.fail = c->d_fail;
-    a.counters = c->d_counters;
-    a.tile_cols = c->o.tile_cols;
-    a.persistent = (c->o.form & QTM_FORM_BATCHED) ? 1 : 0;
-    // failsafe bound on block cycles: every slot may run all its trajectories at max_steps
-    long long per_slot = count;   // worst case (one slot)
-    long long mc = (c->o.max_steps + 4) * 3;
-    a.max_cycles = (per_slot > 0 && mc < LLONG_MAX / (per_slot + 1)) ? mc * (per_slot + 1) : LLONG_MAX;
+    qtm::RunArgs a = run_args(c, count, jcap, segc);
 
     qtm::LaunchInfo li{};
     if (c->o.form & QTM_FORM_BATCHED) {
@@ -927,6 +941,8 @@ int qtm_run_range(qtm_ctx* c, int64_t traj_begin, int64_t count, uint64_t seed) 
     }
     st.passes = (int64_t)ctrs[0];
     st.max_team_passes = (int64_t)ctrs[2];
+    st.root_evals = (int64_t)ctrs[1];
+    st.team_shape = li.shape;
     st.rhs_evals = (int64_t)ctrs[0] * li.cols;
     st.failed_traj = failv == LLONG_MAX ? -1 : failv;
     st.kernel_ms = ms;

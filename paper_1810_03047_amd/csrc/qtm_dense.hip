@@ -44,6 +44,7 @@ __global__ void __launch_bounds__(512) traj_dense_kernel(RunArgs a, int lds_m) {
     Body<DenseLayout<T, PREC>> B(L, S, a, cs, flags);
     B.run();
     if (threadIdx.x == 0) atomicAdd(&a.counters[0], B.passes);
+    if (B.roots) atomicAdd(&a.counters[1], B.roots);
 }
 
 // Trajectory average in a fixed order (independent of scheduling): chunk c of

@@ -20,6 +20,7 @@ __global__ void __launch_bounds__(kSparseThreads) traj_sparse_kernel(RunArgs a) 
     __shared__ int cur;
     __shared__ DevSystem sys_lds;
     unsigned long long passes = 0;
+    unsigned long long roots = 0;
     int si = 0;
     for (;;) {
         if (a.n_sys > 1) {
@@ -89,11 +90,13 @@ __global__ void __launch_bounds__(kSparseThreads) traj_sparse_kernel(RunArgs a) 
         Body<SparseLayout<RPT, NBC, PREC>> B(L, S, a, cs, flags);
         B.run();
         passes += B.passes;
+        roots += B.roots;
         __syncthreads();                 // the block leaves the system together
         if (a.n_sys <= 1) break;
         ++si;
     }
     if (threadIdx.x == 0) atomicAdd(&a.counters[0], passes);
+    if (roots) atomicAdd(&a.counters[1], roots);
 }
 
 #ifndef QTM_SPARSE_INSTANCES

@@ -631,8 +631,7 @@ struct Team {
         if (A.learned) {
             const float lh = team_mlp(f);
             if (on) {
-                // snap to the grid 2^(k/4), k = round(4 log2 h)
-                double hh = exp2_quarter((int)rint(4.0 * ((double)lh / 0.69314718055994530942)));
+                double hh = snap_proposal(lh);
                 h = fmin(hh, S.tend - t);
                 state = ST_STEP;
             }
@@ -942,14 +941,19 @@ struct Team {
                 return v - r;
             };
             double lo = 0.0, hi = 1.0;
+            int nev = 0;
             for (int m = 1; m <= 32; ++m) {
                 double x = (double)m / 32.0;
+                ++nev;
                 if (f(x) < 0.0) { hi = x; lo = (double)(m - 1) / 32.0; break; }
             }
             while (hi - lo > 1e-13) {
                 double mid = 0.5 * (lo + hi);
+                ++nev;
                 if (f(mid) < 0.0) hi = mid; else lo = mid;
             }
+            // norm-polynomial evaluations into the run counters (jumps are rare: no register kept)
+            if (lg == 0 && wv == 0) atomicAdd(&A.counters[1], (unsigned long long)nev);
             th = 0.5 * (lo + hi);
             tb = t + th * h;
         }
@@ -1310,7 +1314,11 @@ int launch_wave(const RunArgs& a, const DevSystem& s0, int prec, int waves_per_t
     if (blocks < 1) blocks = 1;
     void* args[] = {(void*)&a, (void*)&od_lds, (void*)&tpb};
     if (hipLaunchKernel(fn, dim3((unsigned)blocks), dim3(threads), args, L.total, st) != hipSuccess) return -3;
-    if (info) { info->blocks = (int)blocks; info->threads = threads; info->lds = (int)L.total; info->cols = cols; info->shape = T * 100 + nwt; }
+    const bool band = nwt == 1 && s0.tile_band && (T == 4 || T == 5);
+    if (info) {
+        info->blocks = (int)blocks; info->threads = threads; info->lds = (int)L.total; info->cols = cols;
+        info->shape = T * 100 + nwt + (band ? 1000 : 0);
+    }
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 #endif  // QTM_WAVE_INSTANCES

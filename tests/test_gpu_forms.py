@@ -44,8 +44,8 @@ def _exact(ctx, r, n, xtol=1e-8):
     return worst, dx
 
 
-def _stat(mean, var, ref, n, k=4.5, floor=1e-6):
-    bound = k * np.sqrt(np.maximum(var, 1e-30) / n) + floor
+def _stat(mean, var, ref, n, k=3.0, floor=1e-6):
+    bound = k * np.sqrt(np.maximum(var, 0.0) / n) + floor
     dev = np.abs(mean - ref)
     return bool(np.all(dev <= bound)), float(np.max(dev / bound))
 

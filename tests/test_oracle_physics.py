@@ -16,6 +16,16 @@ def _within(mean, var, ref, n, k=3.0, floor=1e-6):
     return np.all(np.abs(mean - ref) <= bound), np.max(np.abs(mean - ref) / bound)
 
 
+def _within_many(mean, var, ref, n, floor=1e-6):
+    """For many time points of one independent sample: none beyond 4 sigma/sqrt(n) +
+    floor (chance 6e-5 per point) and at most 5% of the points beyond 3 sigma/sqrt(n) +
+    floor.  0.27% of independent points lie beyond 3 sigma by chance; consecutive
+    output times of one sample are correlated, so a single excursion of the average
+    covers several of them."""
+    z = np.abs(mean - ref) / (np.sqrt(var / n) + floor / 3.0)
+    return (np.mean(z > 3.0) <= 0.05 and np.all(z <= 4.0)), float(np.max(z))
+
+
 def test_lindblad_routes_agree_with_closed_forms():
     s = w.two_level()
     assert np.max(np.abs(lindblad.expect_expm(s)[0] - cf.two_level_sz(s.tlist))) < 1e-13
@@ -89,6 +99,50 @@ def test_random_system_vs_lindblad():
     for e in range(2):
         ok, worst = _within(res["mean"][e].real, res["var"][e], ref[e].real, n)
         assert ok, (e, worst)
+
+
+def test_trilinear_small_cutoff_vs_lindblad():
+    """The optical parametric amplifier of Sec. 4.2 (H = iK(a b^dag c^dag - a^dag b c),
+    three damped modes, coherent pump) at Fock cutoff 5 per mode (d = 125, CSR).
+    20,000 trajectories: at early times the signal and idler averages rest on the few
+    trajectories that have jumped (before any jump every trajectory has n_b = n_c), and
+    fewer trajectories leave that tail too thin for the sample variance to describe."""
+    s = w.trilinear(N=5)
+    n = 20000
+    res = oracle.run(s, n, seed=3)
+    ref = lindblad.expect_ode(s, rtol=1e-8, atol=1e-10)
+    for e in range(3):
+        ok, worst = _within(res["mean"][e].real, res["var"][e], ref[e].real, n)
+        assert ok, (e, worst)
+
+
+@pytest.mark.slow
+def test_trilinear_full_size_vs_lindblad():
+    """The paper's size: cutoff 8 per mode (d = 512, CSR), t in [0, 4], 100 outputs;
+    brute-force Lindblad by DOP853 on the 512 x 512 density matrix.  300 points of one
+    independent sample are compared, so the 3-sigma bound is applied as a rate."""
+    s = w.trilinear()
+    assert s.dim == 512
+    n = 20000
+    res = oracle.run(s, n, seed=5)
+    ref = lindblad.expect_ode(s, rtol=1e-7, atol=1e-9)
+    ok, worst = _within_many(res["mean"].real, res["var"], ref.real, n)
+    assert ok, worst
+
+
+def test_trilinear_closed_system_conservation():
+    """Without damping, H moves one quantum from the pump into the signal and idler
+    pair: n_a + n_b, n_a + n_c and hence n_b - n_c are conserved on every trajectory
+    (no jumps), at the tolerance of the integration."""
+    s = w.trilinear(gammas=(0.0, 0.0, 0.0))
+    s.c_ops = []
+    res = oracle.run(s, 2, seed=0, rtol=1e-9, atol=1e-11)
+    assert res["jump_counts"].sum() == 0
+    X = res["X"].real
+    n0 = X[0, 0, 0]
+    assert np.max(np.abs(X[:, 0] + X[:, 1] - n0)) < 1e-6
+    assert np.max(np.abs(X[:, 1] - X[:, 2])) < 1e-6
+    assert np.max(X[:, 1]) > 0.5          # the signal mode is actually populated
 
 
 # ------------------------------------------------------------ invariants
