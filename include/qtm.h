@@ -217,6 +217,32 @@ int qtm_traj_stats(const qtm_ctx* ctx, int32_t s, int32_t* stats);
  * Filled also after a run that failed with QTM_E_STEP. */
 int qtm_stats(const qtm_ctx* ctx, qtm_stats_t* st);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same computation as
+ * qtm_run_range on a context of ONE system, with every per-run device buffer
+ * (per-trajectory outputs and counters, queue, averaging partial sums) taken from
+ * a fixed array of QTM_NOALLOC_SCRATCH_MB MiB inside the library, one per device,
+ * held until the process ends.  The call allocates nothing (no hipMalloc, hipFree
+ * or graph capture); trajectories are processed in chunks that fit the array, and
+ * the chunk sums are added in chunk order, so the result does not depend on
+ * scheduling.
+ *   sum    [n_e][n_t] complex (interleaved) sums over the trajectories of
+ *          <psi|O_k|psi>/<psi|psi>, caller-allocated host buffer;
+ *   sumsq  [n_e][n_t] sums of the squared real parts, caller-allocated host buffer.
+ * The mean is sum / count, as qtm_expect forms it from qtm_sums.  Jump logs and
+ * segment records are not kept; qtm_stats describes the call.  Afterwards the
+ * context's per-run read-back calls (qtm_expect, qtm_sums, qtm_traj_expect,
+ * qtm_jumps, qtm_traj_stats, qtm_segments) return QTM_E_STATE until the next
+ * qtm_run.  Every call on one device shares that device's array and leaves the
+ * last call's contents in it: calls that overlap on one device (several host
+ * threads, or several streams in flight) race and must not be made.
+ * Errors: QTM_E_INVAL (batch context of several systems, count < 1, null
+ * buffer, one trajectory's outputs n_e x n_t larger than the array allows),
+ * QTM_E_STATE, QTM_E_DEVICE, QTM_E_STEP as qtm_run. */
+#define QTM_NOALLOC_SCRATCH_MB 32
+int qtm_run_range_noalloc(qtm_ctx* ctx, int64_t traj_begin, int64_t count, uint64_t seed, double* sum,
+                          double* sumsq);
+
 /* ---------------------------------------------------- learned proposal */
 /* The proposal network maps 16 segment-start features to (log h0, log tau_lo,
  * log tau_hi): features are 12 diagonal-observable expectations (the f_ops

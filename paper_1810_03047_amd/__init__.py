@@ -26,6 +26,7 @@ PREC_FP64, PREC_FP32 = 0, 1
 FORM_LEARNED, FORM_BATCHED = 1, 2
 MLP_NPARAM, MLP_NTOTAL = 5443, 5475
 SEG_REC = 20
+NOALLOC_SCRATCH_MB = 32          # QTM_NOALLOC_SCRATCH_MB of include/qtm.h
 
 _FMT = {"dense": 0, "csr": 1, "diag": 2}
 _dp = C.POINTER(C.c_double)
@@ -75,6 +76,7 @@ _SIGS = {
     "qtm_create_batch": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(_System), C.POINTER(_Opts)]),
     "qtm_run": (C.c_int, [C.c_void_p, C.c_int64, C.c_uint64]),
     "qtm_run_range": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.c_uint64]),
+    "qtm_run_range_noalloc": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.c_uint64, _dp, _dp]),
     "qtm_expect": (C.c_int, [C.c_void_p, _dp, _dp]),
     "qtm_expect_system": (C.c_int, [C.c_void_p, C.c_int32, _dp, _dp]),
     "qtm_sums": (C.c_int, [C.c_void_p, C.c_int32, _dp, _dp, C.POINTER(C.c_int64)]),
@@ -224,6 +226,17 @@ class Context:
         _check(load().qtm_run_range(self._h, int(begin), int(count), int(seed)))
         self.last_count = int(count)
         return self
+
+    def run_range_noalloc(self, begin: int, count: int, seed: int = 0):
+        """qtm_run_range_noalloc: (sum [n_e, n_t] complex, sumsq [n_e, n_t]) of the
+        trajectories [begin, begin + count), computed without any device allocation."""
+        _, n_e, n_t = self.dims[0]
+        s = np.zeros((n_e, n_t), dtype=np.complex128)
+        s2 = np.zeros((n_e, n_t))
+        _check(load().qtm_run_range_noalloc(self._h, int(begin), int(count), int(seed),
+                                            _ptr(s.view(np.float64)), _ptr(s2)))
+        self.last_count = 0
+        return s, s2
 
     def expect(self, system: int = 0):
         """(mean [n_e, n_t] complex, var [n_e, n_t])."""

@@ -17,6 +17,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -583,6 +584,54 @@ struct DevScratch {
         return 0;
     }
 };
+
+}  // namespace
+
+// ------------------------------------------------------------------ no-allocation runs
+// Per-run device memory of qtm_run_range_noalloc: a fixed array in the library's code
+// object (one copy per device, alive until the process ends), so that the call never
+// allocates.  Host code must not pass the array's name to a kernel or copy: it stands
+// for a host-side shadow, not the device address; the device address comes from
+// hipGetSymbolAddress, taken once per device.
+constexpr size_t kNoallocScratchBytes = (size_t)QTM_NOALLOC_SCRATCH_MB << 20;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+constexpr int kMaxDevices = 64;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of this device's scratch array (the device must be current).
+int scratch_address(int dev, unsigned char** out) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(QTM_E_DEVICE, "device ordinal %d above %d", dev, kMaxDevices - 1);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return fail(QTM_E_DEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch_dev[dev] = p;
+    }
+    *out = (unsigned char*)g_scratch_dev[dev];
+    return QTM_OK;
+}
+
+// tot += part, element by element (part: one chunk's sums, added in chunk order)
+__global__ void accumulate_kernel(double* tot, const double* part, int n, int first) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) tot[i] = first ? part[i] : tot[i] + part[i];
+}
+
+// out[j] += sum over q of st[q][j] (j < 4), integer sums (order-independent)
+__global__ void tstat_sum_kernel(const int* st, long long count, unsigned long long* out) {
+    unsigned long long s[4] = {0, 0, 0, 0};
+    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < count; q += (long long)gridDim.x * blockDim.x)
+        for (int j = 0; j < 4; ++j) s[j] += (unsigned long long)(unsigned int)st[4 * q + j];
+    for (int j = 0; j < 4; ++j)
+        if (s[j]) atomicAdd(&out[j], s[j]);
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
 
@@ -1163,6 +1212,97 @@ int qtm_train_proposal(qtm_ctx* c, const float* feat, const float* tgt, int64_t 
         std::vector<uint16_t> fr = mlp_fragments(q);
         HIPCHECK(hipMemcpy(c->d_mlpf, fr.data(), sizeof(uint16_t) * fr.size(), hipMemcpyHostToDevice));
     }
+    return QTM_OK;
+}
+
+int qtm_run_range_noalloc(qtm_ctx* c, int64_t traj_begin, int64_t count, uint64_t seed, double* sum, double* sumsq) {
+    if (check_ctx(c)) return QTM_E_INVAL;
+    if (c->sys.size() != 1) return fail(QTM_E_INVAL, "qtm_run_range_noalloc takes a context of one system");
+    if (count < 1 || traj_begin < 0) return fail(QTM_E_INVAL, "need count >= 1 and traj_begin >= 0");
+    if (!sum || !sumsq) return fail(QTM_E_INVAL, "null output buffer");
+    if ((c->o.form & QTM_FORM_LEARNED) && !c->have_mlp) return fail(QTM_E_STATE, "learned form requested before qtm_set_proposal");
+    HIPCHECK(hipSetDevice(c->device));
+    unsigned char* base = nullptr;
+    int rc = scratch_address(c->device, &base);
+    if (rc) return rc;
+    auto t0 = std::chrono::steady_clock::now();
+    // the context's per-run read-back calls refer to qtm_run only
+    c->ran = false;
+    c->last_count = 0;
+    SysHost& S = c->sys[0];
+    const size_t m = (size_t)S.n_e * S.n_t;
+    // scratch layout: [total sums 2m][total sums of squares m][chunk sums 2m][chunk squares m]
+    // [averaging partials][queue][run counters 4][X chunk][counters chunk][jump counts chunk]
+    const int nchunk_max = 256;
+    const size_t o_tsum = 0, o_tsq = o_tsum + align256(16 * m), o_csum = o_tsq + align256(8 * m),
+                 o_csq = o_csum + align256(16 * m), o_part = o_csq + align256(8 * m),
+                 o_queue = o_part + align256(sizeof(double) * std::max(qtm::average_part_size((int)m, nchunk_max),
+                                                                      qtm::average_part_size((int)m, 1))),
+                 o_cnt = o_queue + 256, o_traj = o_cnt + 256;
+    const size_t per_traj = 16 * m + 16 + 4;
+    if (o_traj + align256(per_traj) + 1024 > kNoallocScratchBytes)
+        return fail(QTM_E_INVAL, "one trajectory's outputs (%zu values) do not fit the %d MiB scratch", m, QTM_NOALLOC_SCRATCH_MB);
+    const long long cap = (long long)((kNoallocScratchBytes - o_traj - 1024) / per_traj);   // 1024: alignment of 3 regions
+    const long long chunk = std::min<long long>(cap, count);
+    const size_t o_X = o_traj, o_ts = o_X + align256(16 * m * chunk), o_jn = o_ts + align256(16 * chunk);
+    if (o_jn + align256(4 * chunk) > kNoallocScratchBytes) return fail(QTM_E_INVAL, "scratch layout overflow");
+    hipStream_t st = c->stream;
+    double* tsum = (double*)(base + o_tsum);
+    double* tsq = (double*)(base + o_tsq);
+    double* avg[3] = {(double*)(base + o_part), (double*)(base + o_csum), (double*)(base + o_csq)};
+    unsigned long long* cnt = (unsigned long long*)(base + o_cnt);
+    if (qtm::launch_fill(cnt, 4 * sizeof(unsigned long long), 0, st)) return fail(QTM_E_DEVICE, "fill kernel launch failed");
+    qtm_stats_t stt{};
+    stt.ntraj = count;
+    stt.failed_traj = -1;
+    qtm::LaunchInfo li{};
+    for (long long done = 0; done < count; done += chunk) {
+        const long long n = std::min(chunk, count - done);
+        qtm::DevSystem ds = S.dev;
+        ds.X = (double2*)(base + o_X);
+        ds.tstat = (int*)(base + o_ts);
+        ds.jn = (int*)(base + o_jn);
+        ds.jt = (double*)(base + o_X);      // no jump log or segment records (capacities 0)
+        ds.jc = (int*)(base + o_X);
+        ds.segs = (float*)(base + o_X);
+        ds.queue = (unsigned long long*)(base + o_queue);
+        ds.count = n;
+        ds.traj_begin = traj_begin + done;
+        ds.key0 = seed;
+        S.dev = ds;                       // enqueue_run reads the host copy (qtm_run resets it)
+        HIPCHECK(hipMemcpyAsync(c->d_sys, &ds, sizeof(ds), hipMemcpyHostToDevice, st));
+        qtm::RunArgs a = run_args(c, n, 0, 0);
+        if ((rc = enqueue_run(c, a, n, st, &li, avg))) return rc;
+        const int blk = 256, g = (int)((2 * m + blk - 1) / blk);
+        hipLaunchKernelGGL(accumulate_kernel, dim3(g), dim3(blk), 0, st, tsum, (const double*)avg[1], (int)(2 * m), done == 0 ? 1 : 0);
+        hipLaunchKernelGGL(accumulate_kernel, dim3(g), dim3(blk), 0, st, tsq, (const double*)avg[2], (int)m, done == 0 ? 1 : 0);
+        hipLaunchKernelGGL(tstat_sum_kernel, dim3(64), dim3(256), 0, st, (const int*)ds.tstat, n, cnt);
+        HIPCHECK(hipGetLastError());
+        HIPCHECK(hipStreamSynchronize(st));
+        unsigned long long stamps[2] = {0, 0}, ctrs[4] = {0, 0, 0, 0};
+        long long failv = 0;
+        HIPCHECK(hipMemcpy(stamps, c->d_stamp, sizeof(stamps), hipMemcpyDeviceToHost));
+        HIPCHECK(hipMemcpy(&failv, c->d_fail, sizeof(long long), hipMemcpyDeviceToHost));
+        HIPCHECK(hipMemcpy(ctrs, c->d_counters, sizeof(ctrs), hipMemcpyDeviceToHost));
+        stt.kernel_ms += (double)(stamps[1] - stamps[0]) / (double)c->wall_khz;
+        stt.passes += (int64_t)ctrs[0];
+        stt.root_evals += (int64_t)ctrs[1];
+        stt.max_team_passes = std::max<int64_t>(stt.max_team_passes, (int64_t)ctrs[2]);
+        stt.rhs_evals += (int64_t)ctrs[0] * li.cols;
+        if (failv != LLONG_MAX) {
+            stt.failed_traj = failv;
+            c->st = stt;
+            return fail(QTM_E_STEP, "trajectory %lld failed (max_steps or step-size underflow)", failv);
+        }
+    }
+    unsigned long long tot[4] = {0, 0, 0, 0};
+    HIPCHECK(hipMemcpy(tot, cnt, sizeof(tot), hipMemcpyDeviceToHost));
+    HIPCHECK(hipMemcpy(sum, tsum, sizeof(double) * 2 * m, hipMemcpyDeviceToHost));
+    HIPCHECK(hipMemcpy(sumsq, tsq, sizeof(double) * m, hipMemcpyDeviceToHost));
+    stt.accepted = (int64_t)tot[0]; stt.rejected = (int64_t)tot[1]; stt.segments = (int64_t)tot[2]; stt.jumps = (int64_t)tot[3];
+    stt.blocks = li.blocks; stt.threads = li.threads; stt.tile_cols = li.cols; stt.lds_bytes = li.lds; stt.team_shape = li.shape;
+    stt.elapsed_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    c->st = stt;
     return QTM_OK;
 }
 
