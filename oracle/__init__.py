@@ -55,7 +55,8 @@ def lib(fast: bool = False):
                                  C.POINTER(_Op), C.c_int, C.c_double, C.c_double, C.c_int64,
                                  C.c_uint64, C.c_uint64, C.c_int64, C.c_int64, C.c_int,
                                  _dp, C.POINTER(_Op), C.c_int,
-                                 _dp, C.c_int, _dp, _ip, _ip, _lp, C.c_int, _dp, _lp]
+                                 _dp, C.c_int, _dp, _ip, _ip, _lp, C.c_int, _dp, _lp,
+                                 C.POINTER(_Op), _dp, C.c_int]
         L.qtmref_average.argtypes = [_dp, C.c_int64, C.c_int, C.c_int, _dp, _dp]
         L.qtmref_mlp_nparam.restype = C.c_int
         L.qtmref_mlp_ntotal.restype = C.c_int
@@ -169,7 +170,9 @@ def run(system, ntraj: int, seed: int = 0, sys_id: int = 0, traj_begin: int = 0,
     Returns per-trajectory outputs ``X`` [ntraj, n_e, n_t] (complex), the
     index-ordered average ``mean`` [n_e, n_t] (complex) and ``var`` (of the
     real part), the jump log, per-trajectory stats (accepted, rejected, rhs,
-    segments, jumps), optional segment records and the status.  ``fast`` runs the
+    segments, jumps), optional segment records and the status.  A system with a ``td``
+    attribute (a list of (H_k, (c, a, b, w)) pairs) has the time-dependent Hamiltonian
+    H0 + sum_k (c + a cos(w t) + b sin(w t)) H_k.  ``fast`` runs the
     -O3 AVX2/FMA timing build instead of the parity build.
     """
     s = system
@@ -178,6 +181,10 @@ def run(system, ntraj: int, seed: int = 0, sys_id: int = 0, traj_begin: int = 0,
     ch, carr = _op_array(s.c_ops)
     eh, earr = _op_array(s.e_ops)
     fh, farr = _op_array(f_ops or [])
+    # time-dependent terms H_k with coefficients f_k(t) = c + a cos(w t) + b sin(w t)
+    td = getattr(s, "td", None) or []
+    th, tarr = _op_array([op for op, _ in td])
+    tcoef = np.ascontiguousarray([list(cf) for _, cf in td], dtype=np.float64).reshape(-1) if td else np.zeros(4)
     X = np.zeros((ntraj, n_e, n_t), dtype=np.complex128)
     jt = np.zeros((ntraj, max(1, jcap)))
     jc = np.zeros((ntraj, max(1, jcap)), dtype=np.int32)
@@ -192,7 +199,8 @@ def run(system, ntraj: int, seed: int = 0, sys_id: int = 0, traj_begin: int = 0,
                           rtol, atol, max_steps, seed, sys_id, traj_begin, ntraj, nthreads,
                           _ptr(mp), farr, len(f_ops or []),
                           _ptr(X.view(np.float64)), jcap, _ptr(jt), _ptr(jc, _ip), _ptr(jn, _ip),
-                          _ptr(stats, _lp), seg_cap, _ptr(segs), _ptr(fail, _lp))
+                          _ptr(stats, _lp), seg_cap, _ptr(segs), _ptr(fail, _lp),
+                          tarr, _ptr(tcoef), len(td))
     mean = np.zeros((n_e, n_t), dtype=np.complex128)
     var = np.zeros((n_e, n_t))
     lib().qtmref_average(_ptr(X.view(np.float64)), ntraj, n_e, n_t, _ptr(mean.view(np.float64)), _ptr(var))

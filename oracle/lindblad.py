@@ -10,7 +10,8 @@ Two independent routes:
   vec(A rho B) = (B^T kron A) vec(rho)) exponentiated with scipy.linalg.expm,
   for d up to about 40;
 * ``expect_ode``: the matrix equation integrated with scipy's DOP853 at tight
-  tolerance using sparse operators, for larger d.
+  tolerance using sparse operators, for larger d, and for time-dependent
+  Hamiltonians H(t) = H + sum_k f_k(t) H_k (a system's ``td`` list).
 """
 from __future__ import annotations
 
@@ -78,10 +79,16 @@ def expect_ode(system, rtol: float = 1e-10, atol: float = 1e-12) -> np.ndarray:
     for Cm in Cs:
         Mx = (Mx - 0.5 * (Cm.conj().T @ Cm)).tocsr()
 
-    def rhs(_t, y):
+    # time-dependent terms H_k with coefficients f_k(t) = c + a cos(w t) + b sin(w t)
+    td = [(_sparse(op), cf) for op, cf in (getattr(system, "td", None) or [])]
+
+    def rhs(t, y):
         rho = y.reshape(d, d)
+        Mt = Mx
+        for Hk, (c, a, b, w) in td:
+            Mt = Mt - 1j * (c + a * np.cos(w * t) + b * np.sin(w * t)) * Hk
         # rho M^dag = (M rho^dag)^dag and C rho C^dag = C (C rho^dag)^dag
-        out = Mx @ rho + (Mx @ rho.conj().T).conj().T
+        out = Mt @ rho + (Mt @ rho.conj().T).conj().T
         for Cm in Cs:
             out = out + Cm @ (Cm @ rho.conj().T).conj().T
         return out.reshape(-1)

@@ -31,6 +31,12 @@
  * The learned form replaces only the starting step of each segment by the
  * MLP proposal (16 -> 64 -> 64 -> 3, GELU), evaluated here in FP64 on the
  * same (BF16-rounded) weights, snapped to the grid 2^(k/4).
+ *
+ * Time-dependent Hamiltonians (the right-hand-side function of Sec. 3 receives
+ * the time): H(t) = H0 + sum_k f_k(t) H_k with f_k(t) = c + a cos(w t) + b sin(w t);
+ * the collapse operators stay constant, so M(t) = M0 - i sum_k f_k(t) H_k with
+ * M0 = -i H0 - 1/2 sum_n C_n^dag C_n, and every evaluation of the right-hand side
+ * (DOPRI5 stages at t + c_s h, the starting step's probe at t + h0) takes its time.
  */
 #include <algorithm>
 #include <cfloat>
@@ -74,6 +80,12 @@ void apply(const Op& A, const cd* x, cd* y) {
         for (int i = 0; i < d; ++i) y[i] = A.v[i] * x[i];
     }
 }
+
+// f(t) = c + a cos(w t) + b sin(w t), the coefficient of one time-dependent term
+struct Drive {
+    double c = 0.0, a = 0.0, b = 0.0, w = 0.0;
+    double at(double t) const { return c + a * std::cos(w * t) + b * std::sin(w * t); }
+};
 
 double norm2(const cd* x, int d) {
     double s = 0.0;
@@ -205,9 +217,11 @@ struct Dopri {
 };
 const Dopri& dopri() { static const Dopri t; return t; }
 
-/* One attempted DOPRI5 step from (y, k[0] = M y) with step h.
+/* One attempted DOPRI5 step from (t, y, k[0] = f(t, y)) with step h; f(t, x, out)
+ * evaluates the right-hand side, stage s at time t + c_s h.
  * Fills k[1..6], y_new (the stage-7 input) and the error vector e. */
-void dopri_step(const Op& M, int d, const cd* y, double h, std::vector<std::vector<cd>>& k,
+template <class F>
+void dopri_step(const F& f, double t, int d, const cd* y, double h, std::vector<std::vector<cd>>& k,
                 std::vector<cd>& ynew, std::vector<cd>& e, std::vector<cd>& w) {
     const Dopri& T = dopri();
     for (int s = 1; s < 7; ++s) {
@@ -217,7 +231,7 @@ void dopri_step(const Op& M, int d, const cd* y, double h, std::vector<std::vect
             w[i] = y[i] + h * acc;
         }
         if (s == 6) ynew.assign(w.begin(), w.begin() + d);
-        apply(M, w.data(), k[s].data());
+        f(t + T.c[s] * h, w.data(), k[s].data());
     }
     for (int i = 0; i < d; ++i) {
         cd acc = 0.0;
@@ -258,8 +272,10 @@ struct Dense {
 };
 
 /* Starting step (Hairer-Norsett-Wanner Sec. II.4, with the step limited to
- * the remaining interval).  f0 = M y0 is given; costs one more product. */
-double initial_step(const Op& M, int d, const cd* y0, const cd* f0, double span, double rtol, double atol,
+ * the remaining interval).  f0 = f(t0, y0) is given; costs one more evaluation,
+ * f(t0 + h0, y0 + h0 f0). */
+template <class F>
+double initial_step(const F& f, double t0, int d, const cd* y0, const cd* f0, double span, double rtol, double atol,
                     std::vector<cd>& tmp, std::vector<cd>& f1, int64_t& rhs) {
     double s0 = 0.0, s1 = 0.0;
     for (int i = 0; i < d; ++i) {
@@ -271,7 +287,7 @@ double initial_step(const Op& M, int d, const cd* y0, const cd* f0, double span,
     double h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 / d1;
     h0 = std::min(h0, span);
     for (int i = 0; i < d; ++i) tmp[i] = y0[i] + h0 * f0[i];
-    apply(M, tmp.data(), f1.data());
+    f(t0 + h0, tmp.data(), f1.data());
     ++rhs;
     double s2 = 0.0;
     for (int i = 0; i < d; ++i) {
@@ -387,6 +403,8 @@ double mlp_loss_grad(const Mlp& m, const double* feat, double log_h, double log_
 struct Problem {
     int d = 0, n_c = 0, n_e = 0, n_t = 0;
     Op M;
+    std::vector<Op> Htd;         // time-dependent terms H_k and their coefficients f_k
+    std::vector<Drive> ftd;
     std::vector<Op> C, O, F;     // collapse, expectation, feature (diagonal) operators
     std::vector<cd> psi0;
     std::vector<double> tl;
@@ -395,6 +413,16 @@ struct Problem {
     uint64_t seed = 0, sys_id = 0;
     const double* mlp = nullptr;   // learned form when non-null
 };
+
+/* out = M(t) x = M0 x - i sum_k f_k(t) H_k x  (tmp: scratch of length d) */
+void rhs_at(const Problem& P, double t, const cd* x, cd* out, cd* tmp) {
+    apply(P.M, x, out);
+    for (size_t k = 0; k < P.Htd.size(); ++k) {
+        apply(P.Htd[k], x, tmp);
+        const cd c(0.0, -P.ftd[k].at(t));
+        for (int i = 0; i < P.d; ++i) out[i] += c * tmp[i];
+    }
+}
 
 struct TrajResult {
     int64_t accepted = 0, rejected = 0, rhs = 0, segments = 0, jumps = 0;
@@ -456,7 +484,8 @@ int run_trajectory(const Problem& P, int64_t traj, double* X, int jcap, double* 
     const int d = P.d;
     const double t0 = P.tl[0], tend = P.tl[P.n_t - 1];
     std::vector<std::vector<cd>> k(7, std::vector<cd>(d));
-    std::vector<cd> y(P.psi0), ynew(d), e(d), w(d), tmp(d), f1(d), u(d);
+    std::vector<cd> y(P.psi0), ynew(d), e(d), w(d), tmp(d), f1(d), u(d), scr(d);
+    auto f = [&](double tt, const cd* x, cd* out) { rhs_at(P, tt, x, out, scr.data()); };
     Dense D;
     double t = t0;
     int kk = 0;                       // next output index
@@ -470,7 +499,7 @@ int run_trajectory(const Problem& P, int64_t traj, double* X, int jcap, double* 
         philox4x64_10(ctr, key, rnd);
         const double r = uniform53(rnd[0]), uch = uniform53(rnd[1]);
         R.segments++;
-        apply(P.M, y.data(), k[0].data());
+        f(t, y.data(), k[0].data());
         R.rhs++;
         double h;
         SegRec* rec = (segs && nrec < seg_cap) ? &segs[nrec] : nullptr;
@@ -482,7 +511,7 @@ int run_trajectory(const Problem& P, int64_t traj, double* X, int jcap, double* 
             mlp_forward(m, feat, tp);
             h = std::min(snap_step(tp.o[0]), tend - t);
         } else {
-            h = initial_step(P.M, d, y.data(), k[0].data(), tend - t, P.rtol, P.atol, tmp, f1, R.rhs);
+            h = initial_step(f, t, d, y.data(), k[0].data(), tend - t, P.rtol, P.atol, tmp, f1, R.rhs);
         }
         if (rec) { std::memcpy(rec->f, feat, sizeof(feat)); rec->valid = 1; rec->h_next = -1; rec->censored = 1; rec->tau = 0; nrec++; }
         const double tseg = t;
@@ -493,7 +522,7 @@ int run_trajectory(const Problem& P, int64_t traj, double* X, int jcap, double* 
             if (attempts >= P.max_steps) { R.failed = 1; goto done; }
             bool last = false;
             if (t + h >= tend) { h = tend - t; last = true; }
-            dopri_step(P.M, d, y.data(), h, k, ynew, e, w);
+            dopri_step(f, t, d, y.data(), h, k, ynew, e, w);
             R.rhs += 6;
             ++attempts;
             double err = error_norm(e.data(), y.data(), ynew.data(), d, P.rtol, P.atol);
@@ -637,7 +666,8 @@ int qtmref_dopri_step(int d, const double* Mri, const double* yri, double h, dou
     for (int i = 0; i < d; ++i) y[i] = cd(yri[2 * i], yri[2 * i + 1]);
     std::vector<std::vector<cd>> k(7, std::vector<cd>(d));
     apply(M, y.data(), k[0].data());
-    dopri_step(M, d, y.data(), h, k, ynew, e, w);
+    auto f = [&](double, const cd* x, cd* out) { apply(M, x, out); };
+    dopri_step(f, 0.0, d, y.data(), h, k, ynew, e, w);
     for (int i = 0; i < d; ++i) {
         ynew_out[2 * i] = ynew[i].real(); ynew_out[2 * i + 1] = ynew[i].imag();
         err_vec[2 * i] = e[i].real(); err_vec[2 * i + 1] = e[i].imag();
@@ -666,8 +696,9 @@ int qtmref_integrate_nojump(int d, const double* Mri, const double* yri, double 
     for (int i = 0; i < d; ++i) y[i] = cd(yri[2 * i], yri[2 * i + 1]);
     std::vector<std::vector<cd>> k(7, std::vector<cd>(d));
     apply(M, y.data(), k[0].data());
+    auto f = [&](double, const cd* x, cd* out) { apply(M, x, out); };
     int64_t rhs = 0;
-    double h = first_step > 0.0 ? first_step : initial_step(M, d, y.data(), k[0].data(), tend - t0, rtol, atol, tmp, f1, rhs);
+    double h = first_step > 0.0 ? first_step : initial_step(f, t0, d, y.data(), k[0].data(), tend - t0, rtol, atol, tmp, f1, rhs);
     *h_first = h;
     double t = t0;
     int n = 0, nrej = 0;
@@ -676,7 +707,7 @@ int qtmref_integrate_nojump(int d, const double* Mri, const double* yri, double 
     while (t < tend && guard++ < 10000000) {
         bool last = false;
         if (t + h >= tend) { h = tend - t; last = true; }
-        dopri_step(M, d, y.data(), h, k, ynew, e, w);
+        dopri_step(f, t, d, y.data(), h, k, ynew, e, w);
         double err = error_norm(e.data(), y.data(), ynew.data(), d, rtol, atol);
         if (!(err <= 1.0)) {
             h *= std::isfinite(err) ? std::max(0.2, 0.9 * std::pow(err, -0.2)) : 0.2;
@@ -706,13 +737,16 @@ int qtmref_integrate_nojump(int d, const double* Mri, const double* yri, double 
  *   stats  [ntraj][5]: accepted, rejected, rhs evaluations, segments, jumps (nullable)
  *   mlp    learned-form weights (nullable); f_ops: up to 12 diagonal feature operators
  *   segs   [ntraj][seg_cap][NF + 4] segment records (nullable)
+ *   h_td   n_td time-dependent terms H_k, td_coef [n_td][4] = (c, a, b, w) of
+ *          f_k(t) = c + a cos(w t) + b sin(w t) (nullable when n_td == 0)
  * Returns 0, or -4 when a trajectory failed (smallest failing index in *fail_traj). */
 int qtmref_run(const qtmref_op* H, const qtmref_op* c_ops, int n_c, const double* psi0, const double* tlist,
                int n_t, const qtmref_op* e_ops, int n_e, double rtol, double atol, int64_t max_steps,
                uint64_t seed, uint64_t sys_id, int64_t traj_begin, int64_t ntraj, int nthreads,
                const double* mlp, const qtmref_op* f_ops, int n_f,
                double* X, int jcap, double* jt, int* jc, int* jn, int64_t* stats,
-               int seg_cap, double* segs, int64_t* fail_traj) {
+               int seg_cap, double* segs, int64_t* fail_traj,
+               const qtmref_op* h_td, const double* td_coef, int n_td) {
     Problem P;
     P.d = H->dim; P.n_c = n_c; P.n_e = n_e; P.n_t = n_t;
     Op h = op_from_c(H->fmt, H->dim, H->nnz, H->val, H->row_ptr, H->col_ind);
@@ -720,6 +754,12 @@ int qtmref_run(const qtmref_op* H, const qtmref_op* c_ops, int n_c, const double
     for (int n = 0; n < n_e; ++n) P.O.push_back(op_from_c(e_ops[n].fmt, e_ops[n].dim, e_ops[n].nnz, e_ops[n].val, e_ops[n].row_ptr, e_ops[n].col_ind));
     for (int n = 0; n < n_f; ++n) P.F.push_back(op_from_c(f_ops[n].fmt, f_ops[n].dim, f_ops[n].nnz, f_ops[n].val, f_ops[n].row_ptr, f_ops[n].col_ind));
     P.M = build_M(h, P.C);
+    for (int n = 0; n < n_td; ++n) {
+        P.Htd.push_back(op_from_c(h_td[n].fmt, h_td[n].dim, h_td[n].nnz, h_td[n].val, h_td[n].row_ptr, h_td[n].col_ind));
+        Drive dv;
+        dv.c = td_coef[4 * n]; dv.a = td_coef[4 * n + 1]; dv.b = td_coef[4 * n + 2]; dv.w = td_coef[4 * n + 3];
+        P.ftd.push_back(dv);
+    }
     P.psi0.resize(P.d);
     for (int i = 0; i < P.d; ++i) P.psi0[i] = cd(psi0[2 * i], psi0[2 * i + 1]);
     P.tl.assign(tlist, tlist + n_t);

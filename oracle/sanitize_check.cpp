@@ -93,7 +93,7 @@ int main() {
     std::vector<int64_t> st((size_t)n * 5);
     int64_t fail = 0;
     int rc = qtmref_run(&H.op, &Cm.op, 1, psi0.data(), tl.data(), 101, &Z.op, 1, 1e-6, 1e-8, 1000000, 0, 0, 0, n, 2,
-                        nullptr, nullptr, 0, X.data(), jcap, jt.data(), jc.data(), jn.data(), st.data(), 0, nullptr, &fail);
+                        nullptr, nullptr, 0, X.data(), jcap, jt.data(), jc.data(), jn.data(), st.data(), 0, nullptr, &fail, nullptr, nullptr, 0);
     check(rc == 0 && fail == -1, "two-level run");
     int total = 0;
     for (int q = 0; q < n; ++q) total += jn[q];
@@ -113,11 +113,11 @@ int main() {
     std::vector<double> segs((size_t)n * seg_cap * (NF + 4));
     rc = qtmref_run(&H.op, &Cm.op, 1, psi0.data(), tl.data(), 101, &Z.op, 1, 1e-6, 1e-8, 1000000, 3, 0, 0, n, 2,
                     mlp.data(), &F0.op, 1, X.data(), jcap, jt.data(), jc.data(), jn.data(), st.data(), seg_cap,
-                    segs.data(), &fail);
+                    segs.data(), &fail, nullptr, nullptr, 0);
     check(rc == 0, "learned run");
     mlp[MLP_NPARAM - 3] = -1e4;          // b3[0]: log h0 = -1e4
     rc = qtmref_run(&H.op, &Cm.op, 1, psi0.data(), tl.data(), 101, &Z.op, 1, 1e-6, 1e-8, 1000000, 3, 0, 0, n, 2,
-                    mlp.data(), &F0.op, 1, X.data(), jcap, jt.data(), jc.data(), jn.data(), st.data(), 0, nullptr, &fail);
+                    mlp.data(), &F0.op, 1, X.data(), jcap, jt.data(), jc.data(), jn.data(), st.data(), 0, nullptr, &fail, nullptr, nullptr, 0);
     check(rc == 0, "learned run with a proposal below the step range");
 
     // CSR right-hand side with several channels and a CSR observable (Ising chain, L = 4)
@@ -135,17 +135,25 @@ int main() {
     std::vector<double> X2((size_t)n * 2 * 21 * 2);
     rc = qtmref_run(&Hs.op, cops.data(), (int)cops.size(), p16.data(), tl2.data(), 21, eops2, 2, 1e-6, 1e-8, 1000000, 1,
                     0, 0, n, 2, nullptr, nullptr, 0, X2.data(), jcap, jt.data(), jc.data(), jn.data(), st.data(), 0,
-                    nullptr, &fail);
+                    nullptr, &fail, nullptr, nullptr, 0);
     check(rc == 0, "CSR run");
+
+    // time-dependent Hamiltonian: H0 + (0.3 + 0.5 cos(2 t) + 0.1 sin(2 t)) sigma_x
+    DenseOp Hx(2, {0, 0, 1, 0, 1, 0, 0, 0});
+    const double coef[4] = {0.3, 0.5, 0.1, 2.0};
+    rc = qtmref_run(&H.op, &Cm.op, 1, psi0.data(), tl.data(), 101, &Z.op, 1, 1e-6, 1e-8, 1000000, 5, 0, 0, n, 2,
+                    nullptr, nullptr, 0, X.data(), jcap, jt.data(), jc.data(), jn.data(), st.data(), 0, nullptr, &fail,
+                    &Hx.op, coef, 1);
+    check(rc == 0, "time-dependent run");
 
     // failure paths: max_steps, then a step-size underflow (huge H at t0 = 1e6)
     rc = qtmref_run(&H.op, &Cm.op, 1, psi0.data(), tl.data(), 101, &Z.op, 1, 1e-6, 1e-8, 3, 0, 0, 7, 4, 1,
-                    nullptr, nullptr, 0, X.data(), 0, nullptr, nullptr, jn.data(), st.data(), 0, nullptr, &fail);
+                    nullptr, nullptr, 0, X.data(), 0, nullptr, nullptr, jn.data(), st.data(), 0, nullptr, &fail, nullptr, nullptr, 0);
     check(rc == -4 && fail == 7, "max_steps failure");
     DenseOp Hbig(2, {0, 0, 1e12, 0, 1e12, 0, 0, 0});
     std::vector<double> tl3 = {1e6, 1e6 + 1.0};
     rc = qtmref_run(&Hbig.op, &Cm.op, 1, psi0.data(), tl3.data(), 2, &Z.op, 1, 1e-6, 1e-8, 1000000, 0, 0, 0, 2, 1,
-                    nullptr, nullptr, 0, X.data(), 0, nullptr, nullptr, jn.data(), st.data(), 0, nullptr, &fail);
+                    nullptr, nullptr, 0, X.data(), 0, nullptr, nullptr, jn.data(), st.data(), 0, nullptr, &fail, nullptr, nullptr, 0);
     check(rc == -4 && fail == 0, "step-size underflow failure");
 
     // single step with dense output, the jump-free integrator with a forced rejection

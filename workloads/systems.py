@@ -71,6 +71,9 @@ class System:
     tlist: np.ndarray             # float64 (n_t,), tlist[0] = t0
     e_ops: List[Op]
     meta: dict = field(default_factory=dict)
+    # time-dependent terms: H(t) = H + sum_k f_k(t) H_k with f_k(t) = c + a cos(w t) + b sin(w t),
+    # given as (H_k, (c, a, b, w)) pairs (the right-hand side of the paper's Sec. 3 takes t)
+    td: list = field(default_factory=list)
 
     @property
     def dim(self) -> int:
@@ -308,6 +311,44 @@ def trilinear(N: int = 8, K: float = 1.0, gammas=(0.1, 0.1, 0.4), alpha: float =
     e_ops = [diag(np.real(np.diag(a.conj().T @ a))) for a in (a0, a1, a2)]
     return System("trilinear", csr_from_dense(Hm), cops, psi0, np.linspace(0.0, t_end, n_t),
                   e_ops, dict(N=N, K=K, gammas=gammas, alpha=alpha))
+
+
+def driven_two_level(Delta: float = 1.0, Omega: float = 2.0, omega: float = 1.0, gamma: float = 0.5,
+                     t_end: float = 10.0, n_t: int = 101) -> System:
+    """Two-level atom driven by a classical field without the rotating-wave
+    approximation: H(t) = (Delta/2) sigma_z + Omega cos(omega t) sigma_x,
+    C = sqrt(gamma) sigma_-, psi0 = |g>, observables sigma_z and sigma_x."""
+    sm = np.array([[0, 0], [1, 0]], dtype=np.complex128)
+    s = System("driven_two_level", dense(0.5 * Delta * SZ), [dense(sqrt(gamma) * sm)],
+               np.array([0, 1], dtype=np.complex128), np.linspace(0.0, t_end, n_t),
+               [diag([1.0, -1.0]), dense(SX)], dict(Delta=Delta, Omega=Omega, omega=omega, gamma=gamma))
+    s.td = [(dense(SX), (0.0, Omega, 0.0, omega))]
+    return s
+
+
+def commuting_drive(c: float = 0.3, a: float = 0.8, b: float = -0.4, w: float = 1.7, gamma: float = 0.2,
+                    t_end: float = 6.0, n_t: int = 61) -> System:
+    """H(t) = f(t) sigma_x with f(t) = c + a cos(w t) + b sin(w t) and C = sqrt(gamma) I:
+    the no-jump state is exp(-i F(t) sigma_x) psi0 e^(-gamma t / 2) with F the integral
+    of f, jumps leave the normalised state unchanged, so <sigma_z>(t) = cos(2 F(t))
+    on every trajectory for psi0 = |e>."""
+    s = System("commuting_drive", dense(np.zeros((2, 2), dtype=np.complex128)),
+               [dense(sqrt(gamma) * np.eye(2, dtype=np.complex128))], np.array([1, 0], dtype=np.complex128),
+               np.linspace(0.0, t_end, n_t), [diag([1.0, -1.0])], dict(c=c, a=a, b=b, w=w, gamma=gamma))
+    s.td = [(dense(SX), (c, a, b, w))]
+    return s
+
+
+def driven_jaynes_cummings(N: int = 20, eps: float = 0.3, omega_d: float = 1.0, t_end: float = 20.0,
+                           n_t: int = 201, **kw) -> System:
+    """The Jaynes-Cummings system of jaynes_cummings() with the cavity driven by a
+    classical field: H(t) = H_JC + eps cos(omega_d t) (a + a^dag) (d = 2 N, dense)."""
+    s = jaynes_cummings(N=N, t_end=t_end, n_t=n_t, **kw)
+    a = np.kron(destroy(N), np.eye(2, dtype=np.complex128))
+    s.name = "driven_jaynes_cummings"
+    s.td = [(dense(a + a.conj().T), (0.0, eps, 0.0, omega_d))]
+    s.meta.update(eps=eps, omega_d=omega_d)
+    return s
 
 
 def by_name(name: str, **kw) -> System:
