@@ -7,6 +7,13 @@ alpha = 2 with the atom excited, t in [0, 50] with 501 output times, 10,000
 trajectories, rtol 1e-6, atol 1e-8.  Inputs are synthetic and resident on the
 device before timing starts.
 
+The line also nests, under "secondary", the same measurement (plain FP64 form
+against the batched FP32 form, roofline, CPU baseline and oracle check) for the
+driven two-level atom (500 trajectories), the transverse-field Ising chain
+(L = 10, d = 1024, CSR, 20,000 trajectories), the heterogeneous batch (64
+systems, d 8..256, 500 trajectories each) and the paper's trilinear Hamiltonian
+(d = 512, CSR, 20,000 trajectories).
+
 Forms: "plain" (FP64 products, the starting-step rule at every segment start)
 and the headline "learned+batched+mixed" (FP32 products with FP64 state,
 norms, root finding and averages, persistent teams with slot refill, and the
@@ -25,7 +32,8 @@ capturable).  HIP events (torch.cuda.Event) on the same stream around each whole
 run are reported beside it as run_event_ms (that span also holds the output
 clearing, the averaging and the read-back of the sums).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--forms plain,best]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--forms plain,best] [--no-secondary]
+    python bench.py --workload two_level|tfim|hetero|trilinear     (one configuration alone)
 """
 import argparse
 import json
@@ -270,66 +278,153 @@ def _working_params(p32):
     return p.astype(np.float64)
 
 
-def other_workload(a, qtm, w, torch):
-    """Secondary configurations, one JSON line each (same keys):
-    tfim   -- transverse-field Ising chain L = 10 (d = 1024, CSR), 20,000 trajectories,
-              t in [0, 20]; plain FP64 vs batched + FP32 products (SpMM kernel);
-    hetero -- 64 random systems (d 8..256, 1-4 dense jump operators), 500 trajectories
-              each, t in [0, 20]; per-system launches (FP64) vs the batched tile-class
-              launches with FP32 products."""
-    if a.workload == "tfim":
-        target, n, label = w.tfim(), 20_000, "tfim L=10 (d=1024, CSR, nnz 11264), J=1, h=0.8, gamma=0.05, t in [0,20] (201 points), 20000 trajectories"
-        make = lambda o: qtm.create_system(target, o)
-        run = lambda ctx, seed: ctx.run(n, seed)
-        nnz = int(len(target.H.col_ind))          # M = -i H_eff has the pattern of H (its diagonal is stored)
-        flops = lambda st: (st["accepted"] + st["rejected"]) * (6 * 8.0 * nnz + 128.0 * target.dim)
-    else:
-        target, n, label = w.hetero_batch(), 500, "hetero_batch 64 systems d~U{8..256}, n_c~U{1..4}, t in [0,20] (101 points), 500 trajectories each"
-        make = lambda o: qtm.create_batch(target, o)
-        run = lambda ctx, seed: ctx.run(n, seed)
+def _nnz_M(system) -> int:
+    """Stored entries of M = -i H - 1/2 sum C^dag C (the union of the patterns)."""
+    M = (system.H.to_dense() != 0)
+    for c in system.c_ops:
+        C = c.to_dense()
+        M = M | ((C.conj().T @ C) != 0)
+    return int(M.sum())
 
-        def flops(st, ctx=None):
-            tot = 0.0
-            for si, sy in enumerate(target):
-                ts = ctx.traj_stats(si)
-                tot += float(ts[:, 0].sum() + ts[:, 1].sum()) * (6 * 8.0 * sy.dim ** 2 + 128.0 * sy.dim)
-            return tot
-    total = n * (len(target) if a.workload == "hetero" else 1)
+
+def secondary_spec(name, qtm, w):
+    """The other configurations: (systems, trajectories per system, label, kernel, roofline
+    bound, peak in TFLOP/s or None, flop per trajectory-step of system s or None)."""
+    if name == "two_level":
+        s = [w.two_level()]
+        return dict(systems=s, n=500, batch=False, kernel="traj_team_kernel", bound=None, peak=None, fps=None, check_n=500,
+                    label="driven two-level atom, Omega=1, gamma=0.5, t in [0,10] (101 points), sigma_z, "
+                          "500 trajectories (latency bound: about 40 dependent steps of a 2x2 system)")
+    if name == "tfim":
+        s = [w.tfim()]
+        nnz = _nnz_M(s[0])
+        return dict(systems=s, n=20_000, batch=False, kernel="traj_sparse_kernel", bound="alu", peak=PEAK_FP32_VALU,
+                    fps=[6 * 8.0 * nnz + 128.0 * s[0].dim], check_n=2000,
+                    label=f"tfim L=10 (d=1024, CSR, nnz(M) {nnz}), J=1, h=0.8, gamma=0.05, t in [0,20] "
+                          "(201 points), 20000 trajectories")
+    if name == "trilinear":
+        s = [w.trilinear()]
+        nnz = _nnz_M(s[0])
+        return dict(systems=s, n=20_000, batch=False, kernel="traj_sparse_kernel", bound="alu", peak=PEAK_FP32_VALU,
+                    fps=[6 * 8.0 * nnz + 128.0 * s[0].dim], check_n=20_000,
+                    label=f"trilinear (Sec. 4.2) cutoff 8 per mode (d=512, CSR, nnz(M) {nnz}), K=1, "
+                          "gamma=(0.1,0.1,0.4), alpha=sqrt(3), t in [0,4] (100 points), 20000 trajectories")
+    if name == "hetero":
+        s = w.hetero_batch()
+        return dict(systems=s, n=500, batch=True, kernel="traj_team_batch_kernel (three tile classes)", bound="mfma",
+                    peak=PEAK["fp32"], fps=[6 * 8.0 * x.dim ** 2 + 128.0 * x.dim for x in s], check_n=500,
+                    label="hetero_batch 64 systems d~U{8..256}, n_c~U{1..4}, t in [0,20] (101 points), "
+                          "500 trajectories each")
+    raise ValueError(name)
+
+
+def run_secondary(name, qtm, w, torch, steps, warmup, cpu=True):
+    """Plain FP64 form against the batched FP32 form on one configuration: the same keys
+    as the headline line (value = the batched FP32 form's trajectories/s)."""
+    sp = secondary_spec(name, qtm, w)
+    systems, n = sp["systems"], sp["n"]
+    total = n * len(systems)
+    make = (lambda o: qtm.create_batch(systems, o)) if sp["batch"] else (lambda o: qtm.create_system(systems[0], o))
     out = {}
-    for name, o in (("plain", qtm.Opts(precision=qtm.PREC_FP64)),
-                    ("best", qtm.Opts(precision=qtm.PREC_FP32, form=qtm.FORM_BATCHED))):
+    for form_name, o in (("plain", qtm.Opts(precision=qtm.PREC_FP64)),
+                         ("best", qtm.Opts(precision=qtm.PREC_FP32, form=qtm.FORM_BATCHED))):
         ctx = make(o)
-        for i in range(a.warmup):
-            run(ctx, 1000 + i)
+        for i in range(warmup):
+            ctx.run(n, 1000 + i)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        kms, fl = [], []
-        for i in range(a.steps):
-            run(ctx, i)
+        kms, fl, units = [], [], 0
+        for i in range(steps):
+            ctx.run(n, i)
             st = ctx.stats()
             kms.append(st["kernel_ms"])
-            fl.append(flops(st, ctx) if a.workload == "hetero" else flops(st))
+            units += st["accepted"] + st["rejected"]
+            if sp["fps"] is not None:
+                f = 0.0
+                for si in range(len(systems)):
+                    ts = ctx.traj_stats(si)
+                    f += float(ts[:, 0].sum() + ts[:, 1].sum()) * sp["fps"][si]
+                fl.append(f)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        out[name] = dict(value=total * a.steps / wall, ms=wall / a.steps * 1e3, kernel_ms=float(np.mean(kms)),
-                         tflops=float(np.mean(fl)) / (float(np.mean(kms)) * 1e-3) / 1e12)
+        r = dict(value=total * steps / wall, ms=wall / steps * 1e3, kernel_ms=float(np.mean(kms)),
+                 traj_steps_per_launch=units / steps)
+        if fl:
+            r["tflops"] = float(np.mean(fl)) / (float(np.mean(kms)) * 1e-3) / 1e12
+        else:
+            r["kernel_us_per_team_pass"] = 1e3 * float(np.mean(kms)) / max(1, st["max_team_passes"])
+        out[form_name] = r
         ctx.destroy()
     b = out["best"]
-    # the sparse kernel is bound by vector ALU work (non-packed FP32); the tile classes by
-    # the FP32 matrix cores
-    peak = PEAK_FP32_VALU if a.workload == "tfim" else PEAK["fp32"]
     line = {
-        "metric": METRIC, "value": b["value"], "unit": "trajectories/s", "n_gpus": 1, "steps": a.steps,
-        "warmup": a.warmup, "ms_per_step": b["ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "metric": METRIC, "value": b["value"], "unit": "trajectories/s", "n_gpus": 1, "steps": steps,
+        "warmup": warmup, "ms_per_step": b["ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 products, f64 state", "data": "synthetic",
-        "config": {"workload": label, "ntraj": total, "form": "batched+mixed", "parallelism": "trajectories (1 GPU)"},
-        "roofline": {"bound": "alu" if a.workload == "tfim" else "mfma", "achieved": b["tflops"], "peak": peak,
-                     "unit": "TFLOP/s", "frac": b["tflops"] / peak, "traffic": None,
-                     "kernel": "traj_sparse_kernel" if a.workload == "tfim" else "traj_team_batch_kernel + traj_sparse_kernel",
-                     "kernel_ms": b["kernel_ms"]},
+        "config": {"workload": sp["label"], "ntraj": total, "form": "batched+mixed", "parallelism": "trajectories (1 GPU)"},
         "plain": out["plain"], "speedup_vs_plain": b["value"] / out["plain"]["value"],
     }
-    print(json.dumps(line), flush=True)
+    if sp["peak"] is not None:
+        line["roofline"] = {"bound": sp["bound"], "achieved": b["tflops"], "peak": sp["peak"], "unit": "TFLOP/s",
+                            "frac": b["tflops"] / sp["peak"], "traffic": None, "kernel": sp["kernel"],
+                            "kernel_ms": b["kernel_ms"]}
+    else:
+        line["roofline"] = None
+        line["latency"] = {"kernel": sp["kernel"], "kernel_ms": b["kernel_ms"],
+                           "us_per_team_pass": b["kernel_us_per_team_pass"]}
+    if cpu:
+        line["cpu_baseline"] = cpu_baseline_systems(systems, n)
+        # the oracle on the first trajectories of timed seed 0 of every system, against the
+        # batched FP32 form on the same trajectories
+        line["oracle_check"] = oracle_check_systems(qtm, systems, sp["batch"], sp["check_n"])
+    return line
+
+
+def cpu_baseline_systems(systems, n, cpu_s: float = 15.0):
+    """The oracle (parity build, the faster one on this workload family) on all permitted
+    threads over a bounded sample: the first trajectories of seed 0 of every system."""
+    import oracle
+    threads, nproc, share = _threads()
+    t0 = time.perf_counter()
+    for si, s in enumerate(systems):
+        oracle.run(s, 4, seed=0, sys_id=si, nthreads=threads)
+    dt = time.perf_counter() - t0             # 4 trajectories of each system
+    per = max(4, min(n, int(4 * cpu_s / max(dt * threads, 1e-3))))
+    t0 = time.perf_counter()
+    for si, s in enumerate(systems):
+        oracle.run(s, per, seed=0, sys_id=si, nthreads=threads)
+    wall = time.perf_counter() - t0
+    return {"value": per * len(systems) / wall, "unit": "trajectories/s", "cores": threads, "kind": "oracle",
+            "sample": f"trajectories 0..{per - 1} of each of the {len(systems)} system(s) (seed 0), FP64 C++ "
+                      f"oracle (parity build), {threads} OpenMP threads (nproc {nproc}), {wall:.1f} s"}
+
+
+def oracle_check_systems(qtm, systems, batch, m):
+    """The batched FP32 form against the oracle (parity build) on trajectories 0..m-1 of
+    seed 0 of every system: worst deviation of the averages in units of the bound
+    3 sigma/sqrt(N) + 1e-6, and the fraction of trajectories with the oracle's jump
+    counts."""
+    import oracle
+    threads, _, _ = _threads()
+    o = qtm.Opts(precision=qtm.PREC_FP32, form=qtm.FORM_BATCHED, record_jumps=32)
+    ctx = qtm.create_batch(systems, o) if batch else qtm.create_system(systems[0], o)
+    ctx.run(m, 0)
+    worst, same, tot = 0.0, 0, 0
+    for si, s in enumerate(systems):
+        mean, _ = ctx.expect(si)
+        r = oracle.run(s, m, seed=0, sys_id=si, nthreads=threads, jcap=32)
+        bound = 3.0 * np.sqrt(np.maximum(r["var"], 0.0) / m) + 1e-6
+        worst = max(worst, float(np.max(np.abs(mean.real - r["mean"].real) / bound)))
+        jn = np.array([ctx.jumps(i, system=si)[2] for i in range(m)])
+        same += int(np.sum(jn == r["jump_counts"]))
+        tot += m
+    ctx.destroy()
+    return {"ntraj_per_system": m, "seed": 0, "max_dev_over_bound": worst, "within_bound": worst <= 1.0,
+            "identical_jump_counts": same / tot}
+
+
+def other_workload(a, qtm, w, torch):
+    """One secondary configuration as its own JSON line (--workload NAME)."""
+    print(json.dumps(run_secondary(a.workload, qtm, w, torch, a.steps, a.warmup, cpu=not a.no_cpu)), flush=True)
 
 
 def main():
@@ -344,8 +439,10 @@ def main():
     ap.add_argument("--counters", action="store_true",
                     help="short run for rocprofv3 counter passes: two launches of the headline kernel "
                          "(FP32 products, batched, 10,000 trajectories) and a 256 MiB device copy for calibration")
-    ap.add_argument("--workload", default="jcm", choices=["jcm", "tfim", "hetero"],
-                    help="jcm (default, the headline) or a secondary configuration")
+    ap.add_argument("--workload", default="jcm", choices=["jcm", "two_level", "tfim", "hetero", "trilinear"],
+                    help="jcm (default, the headline) or a secondary configuration alone")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="leave out the secondary configurations nested in the headline line")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: trajectories are independent and the multi-GPU path "
@@ -455,6 +552,15 @@ def main():
         if "plain" in res:
             checks["plain"] = oracle_check(qtm, system, opts_plain, None, NTRAJ, seed=0)
         line["oracle_check"] = checks
+    if not a.no_secondary:
+        # the other configurations (two-level atom, Ising chain, heterogeneous batch,
+        # trilinear Hamiltonian), each with its plain form, roofline, CPU baseline and
+        # oracle check, nested in the one line
+        line["secondary"] = {}
+        for name in ("two_level", "tfim", "hetero", "trilinear"):
+            t0 = time.perf_counter()
+            line["secondary"][name] = run_secondary(name, qtm, w, torch, max(2, min(a.steps, 3)), 1, cpu=not a.no_cpu)
+            print(f"[bench] secondary {name} done in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     print(json.dumps(line), flush=True)
 
 

@@ -150,6 +150,30 @@ void qtm_opts_default(qtm_opts* o);
 int qtm_create(qtm_ctx** out, const qtm_op* H, const qtm_op* c_ops, int32_t n_c, const double* psi0,
                const double* tlist, int32_t n_t, const qtm_op* e_ops, int32_t n_e, const qtm_opts* o);
 
+/* Coefficient of a time-dependent Hamiltonian term: f(t) = c + a cos(omega t) +
+ * b sin(omega t). */
+typedef struct {
+    double c, a, b, omega;
+} qtm_drive;
+#define QTM_MAX_TD 4
+
+/* Creates a context for one system with a time-dependent Hamiltonian
+ *     H(t) = H0 + sum_k f_k(t) H_k,   k < n_td <= QTM_MAX_TD,
+ * the case the paper's right-hand-side function supports by receiving the time
+ * (Sec. 3, and the remark on the time argument after the trilinear example of
+ * Sec. 4.2); the collapse operators stay constant, so H_eff(t) = H(t) - (i/2)
+ * sum_n C_n^dag C_n.  Every evaluation of the right-hand side uses its own time
+ * (Runge-Kutta stage s at t + c_s h).
+ *   H0, c_ops, psi0, tlist, e_ops, o  as for qtm_create;
+ *   H_td   n_td Hermitian d x d operators H_k (any format);
+ *   f_td   n_td coefficient functions (host array).
+ * Supported on the small dense kernel only: d <= 64 (any operator format).
+ * Errors: as qtm_create; QTM_E_INVAL also for n_td outside [1, QTM_MAX_TD], d > 64,
+ * a non-finite coefficient. */
+int qtm_create_td(qtm_ctx** out, const qtm_op* H0, const qtm_op* H_td, const qtm_drive* f_td, int32_t n_td,
+                  const qtm_op* c_ops, int32_t n_c, const double* psi0, const double* tlist, int32_t n_t,
+                  const qtm_op* e_ops, int32_t n_e, const qtm_opts* o);
+
 /* Creates a context holding n_sys systems of mixed dimension (each dense,
  * d <= 256, n_e <= 16) that qtm_run integrates in one persistent launch per
  * tile class.  System s uses Philox key (seed, s).  Errors as qtm_create; the

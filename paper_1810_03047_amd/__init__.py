@@ -61,6 +61,10 @@ class _Stats(C.Structure):
                 ("team_shape", C.c_int32), ("reserved_stats", C.c_int32)]
 
 
+class _Drive(C.Structure):
+    _fields_ = [("c", C.c_double), ("a", C.c_double), ("b", C.c_double), ("omega", C.c_double)]
+
+
 class _System(C.Structure):
     _fields_ = [("H", C.POINTER(_Op)), ("c_ops", C.POINTER(_Op)), ("n_c", C.c_int32), ("psi0", _dp),
                 ("tlist", _dp), ("n_t", C.c_int32), ("e_ops", C.POINTER(_Op)), ("n_e", C.c_int32)]
@@ -74,6 +78,9 @@ _SIGS = {
     "qtm_create": (C.c_int, [C.POINTER(C.c_void_p), C.POINTER(_Op), C.POINTER(_Op), C.c_int32, _dp, _dp, C.c_int32,
                              C.POINTER(_Op), C.c_int32, C.POINTER(_Opts)]),
     "qtm_create_batch": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(_System), C.POINTER(_Opts)]),
+    "qtm_create_td": (C.c_int, [C.POINTER(C.c_void_p), C.POINTER(_Op), C.POINTER(_Op), C.POINTER(_Drive), C.c_int32,
+                                C.POINTER(_Op), C.c_int32, _dp, _dp, C.c_int32, C.POINTER(_Op), C.c_int32,
+                                C.POINTER(_Opts)]),
     "qtm_run": (C.c_int, [C.c_void_p, C.c_int64, C.c_uint64]),
     "qtm_run_range": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.c_uint64]),
     "qtm_run_range_noalloc": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.c_uint64, _dp, _dp]),
@@ -328,8 +335,31 @@ def create(H, c_ops, psi0, tlist, e_ops, opts: Optional[Opts] = None) -> Context
     return Context(h, [(int(H.dim), len(e_ops), len(tl))], opts)
 
 
+def create_td(H0, td, c_ops, psi0, tlist, e_ops, opts: Optional[Opts] = None) -> Context:
+    """qtm_create_td: H(t) = H0 + sum_k f_k(t) H_k, td = [(H_k, (c, a, b, omega)), ...] with
+    f_k(t) = c + a cos(omega t) + b sin(omega t)."""
+    opts = opts or Opts()
+    L = load()
+    hh, harr = _ops([H0])
+    th, tarr = _ops([op for op, _ in td])
+    drv = (_Drive * max(1, len(td)))(*[_Drive(*[float(x) for x in cf]) for _, cf in td])
+    ch, carr = _ops(c_ops)
+    eh, earr = _ops(e_ops)
+    psi = np.ascontiguousarray(np.asarray(psi0, dtype=np.complex128)).view(np.float64)
+    tl = np.ascontiguousarray(tlist, dtype=np.float64)
+    h = C.c_void_p()
+    o = opts._c()
+    _check(L.qtm_create_td(C.byref(h), harr, tarr, drv, len(td), carr, len(c_ops), _ptr(psi), _ptr(tl), len(tl),
+                           earr, len(e_ops), C.byref(o)))
+    return Context(h, [(int(H0.dim), len(e_ops), len(tl))], opts)
+
+
 def create_system(system, opts: Optional[Opts] = None) -> Context:
-    """qtm_create from an object with H, c_ops, psi0, tlist, e_ops attributes."""
+    """qtm_create (or qtm_create_td when the system has time-dependent terms ``td``) from an
+    object with H, c_ops, psi0, tlist, e_ops attributes."""
+    td = getattr(system, "td", None)
+    if td:
+        return create_td(system.H, td, system.c_ops, system.psi0, system.tlist, system.e_ops, opts)
     return create(system.H, system.c_ops, system.psi0, system.tlist, system.e_ops, opts)
 
 

@@ -46,6 +46,10 @@ __device__ __forceinline__ constexpr double dp_a(int s, int j) {
                    : j == 4 ? -2187.0 / 6784 : j == 5 ? 11.0 / 84 : 0.0)
          : 0.0;
 }
+// nodes c_s: stage s evaluates the right-hand side at t + c_s h
+__device__ __forceinline__ constexpr double dp_c(int s) {
+    return s == 1 ? 1.0 / 5 : s == 2 ? 3.0 / 10 : s == 3 ? 4.0 / 5 : s == 4 ? 8.0 / 9 : s >= 5 ? 1.0 : 0.0;
+}
 // error weights e_j = b_j - b*_j (7 stages)
 __device__ __forceinline__ constexpr double dp_e(int j) {
     return j == 0 ? 35.0 / 384 - 5179.0 / 57600 : j == 1 ? 0.0 : j == 2 ? 500.0 / 1113 - 7571.0 / 16695
@@ -174,12 +178,14 @@ template <> struct MfmaT<0> {
     __device__ static acc_t op(in_t a, in_t b, acc_t c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
     __device__ static const in_t* frag(const DevSystem& s) { return s.Mfrag; }
     __device__ static const in_t* team(const DevSystem& s) { return s.Mteam; }
+    __device__ static const in_t* td(const DevSystem& s) { return s.Mtd; }
 };
 template <> struct MfmaT<1> {
     typedef float in_t; typedef f4 acc_t;
     __device__ static acc_t op(in_t a, in_t b, acc_t c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
     __device__ static const in_t* frag(const DevSystem& s) { return s.Mfrag32; }
     __device__ static const in_t* team(const DevSystem& s) { return s.Mteam32; }
+    __device__ static const in_t* td(const DevSystem& s) { return s.Mtd32; }
 };
 
 // Dense layout: wave w handles column tile ct = w / wpc (16 columns, one per

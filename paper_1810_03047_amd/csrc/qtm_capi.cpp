@@ -305,7 +305,15 @@ int ensure_buf(DevBuf& b, size_t bytes) {
     return QTM_OK;
 }
 
-int setup_system(SysHost& S, const qtm_system& in, int idx, const qtm_opts& o, bool want_ell) {
+// Time-dependent terms of one system (qtm_create_td).
+struct TdSpec {
+    const qtm_op* H = nullptr;
+    const qtm_drive* f = nullptr;
+    int n = 0;
+};
+
+int setup_system(SysHost& S, const qtm_system& in, int idx, const qtm_opts& o, bool want_ell,
+                 const TdSpec* td = nullptr) {
     const qtm_op* H = in.H;
     if (!H) return fail(QTM_E_INVAL, "system %d: null H", idx);
     const int d = H->dim;
@@ -334,6 +342,21 @@ int setup_system(SysHost& S, const qtm_system& in, int idx, const qtm_opts& o, b
     // MFMA block kernel (d <= 128), or the SpMM kernel on full rows (d <= 2048)
     S.sparse = H->fmt == QTM_FMT_CSR || d > 128;
     S.team = !S.sparse && qtm::wave_supported(d);
+    const int n_td = td ? td->n : 0;
+    if (n_td) {
+        if (n_td < 0 || n_td > QTM_MAX_TD) return fail(QTM_E_INVAL, "n_td = %d outside [1, %d]", n_td, QTM_MAX_TD);
+        if (!td->H || !td->f) return fail(QTM_E_INVAL, "null time-dependent terms");
+        if (!qtm::wave_supported(d))
+            return fail(QTM_E_INVAL, "time-dependent terms need d <= 64 (the small dense kernel); d = %d", d);
+        for (int k = 0; k < n_td; ++k) {
+            if ((rc = validate_op(&td->H[k], d, "H_td", k))) return rc;
+            const qtm_drive& f = td->f[k];
+            if (!std::isfinite(f.c) || !std::isfinite(f.a) || !std::isfinite(f.b) || !std::isfinite(f.omega))
+                return fail(QTM_E_INVAL, "f_td[%d]: non-finite coefficient", k);
+        }
+        S.sparse = false;                   // every format goes to the small dense kernel
+        S.team = true;
+    }
     if (d > 2048) return fail(QTM_E_INVAL, "system %d: dimension %d above the supported 2048", idx, d);
     S.d = d; S.n_c = in.n_c; S.n_e = in.n_e; S.n_t = in.n_t;
     S.tlist.assign(in.tlist, in.tlist + in.n_t);
@@ -354,6 +377,27 @@ int setup_system(SysHost& S, const qtm_system& in, int idx, const qtm_opts& o, b
             if ((rc = upload(S, &D.Mfrag32, build_frag_team<float>(M, dp, 1)))) return rc;
             D.Mteam = D.Mfrag;
             D.Mteam32 = D.Mfrag32;
+            if (n_td) {
+                // fragments of the right-hand-side matrices -i H_k, one after the other, and
+                // the coefficients (c, a, b, omega) of f_k
+                std::vector<double> t64;
+                std::vector<float> t32;
+                std::vector<double> coef;
+                for (int k = 0; k < n_td; ++k) {
+                    HCsr hk = to_csr(&td->H[k], true);
+                    for (auto& z : hk.v) z *= cd(0.0, -1.0);
+                    const std::vector<double> a = build_frag_team<double>(hk, dp, 0);
+                    const std::vector<float> b = build_frag_team<float>(hk, dp, 1);
+                    t64.insert(t64.end(), a.begin(), a.end());
+                    t32.insert(t32.end(), b.begin(), b.end());
+                    const qtm_drive& f = td->f[k];
+                    coef.insert(coef.end(), {f.c, f.a, f.b, f.omega});
+                }
+                if ((rc = upload(S, &D.Mtd, t64))) return rc;
+                if ((rc = upload(S, &D.Mtd32, t32))) return rc;
+                if ((rc = upload(S, &D.td, coef))) return rc;
+                D.n_td = n_td;
+            }
         } else {
             if ((rc = upload(S, &D.Mfrag, build_frag<double>(M, dp, 0)))) return rc;
             if ((rc = upload(S, &D.Mfrag32, build_frag<float>(M, dp, 1)))) return rc;
@@ -661,7 +705,8 @@ int qtm_tile_candidates(int32_t d, int32_t* waves, int32_t cap) {
     return n;
 }
 
-static int create_common(qtm_ctx** out, int32_t n_sys, const qtm_system* sys, const qtm_opts* o, bool batch) {
+static int create_common(qtm_ctx** out, int32_t n_sys, const qtm_system* sys, const qtm_opts* o, bool batch,
+                         const TdSpec* td = nullptr) {
     if (!out) return fail(QTM_E_INVAL, "null output pointer");
     *out = nullptr;
     qtm_opts opt;
@@ -693,7 +738,7 @@ static int create_common(qtm_ctx** out, int32_t n_sys, const qtm_system* sys, co
     }
     c->sys.resize(n_sys);
     for (int s = 0; s < n_sys; ++s) {
-        int rc = setup_system(c->sys[s], sys[s], s, opt, batch);
+        int rc = setup_system(c->sys[s], sys[s], s, opt, batch, td);
         if (rc) { qtm_destroy(c); return rc; }
     }
     if (batch && n_sys > 1) {
@@ -736,6 +781,16 @@ int qtm_create(qtm_ctx** out, const qtm_op* H, const qtm_op* c_ops, int32_t n_c,
                const double* tlist, int32_t n_t, const qtm_op* e_ops, int32_t n_e, const qtm_opts* o) {
     qtm_system s{H, c_ops, n_c, psi0, tlist, n_t, e_ops, n_e};
     return create_common(out, 1, &s, o, false);
+}
+
+int qtm_create_td(qtm_ctx** out, const qtm_op* H0, const qtm_op* H_td, const qtm_drive* f_td, int32_t n_td,
+                  const qtm_op* c_ops, int32_t n_c, const double* psi0, const double* tlist, int32_t n_t,
+                  const qtm_op* e_ops, int32_t n_e, const qtm_opts* o) {
+    if (n_td < 1 || n_td > QTM_MAX_TD) return fail(QTM_E_INVAL, "n_td = %d outside [1, %d]", n_td, QTM_MAX_TD);
+    qtm_system s{H0, c_ops, n_c, psi0, tlist, n_t, e_ops, n_e};
+    TdSpec td;
+    td.H = H_td; td.f = f_td; td.n = n_td;
+    return create_common(out, 1, &s, o, false, &td);
 }
 
 int qtm_create_batch(qtm_ctx** out, int32_t n_sys, const qtm_system* sys, const qtm_opts* o) {

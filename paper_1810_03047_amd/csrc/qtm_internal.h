@@ -8,6 +8,7 @@ namespace qtm {
 
 constexpr int kMaxE = 16;        // expectation operators per system
 constexpr int kMaxC = 16;        // collapse operators per system
+constexpr int kMaxTD = 4;        // time-dependent Hamiltonian terms per system
 constexpr int kNVMax = 16;       // values per column in one block reduction
 constexpr int kNF = 16, kNH = 64, kNO = 3;   // proposal network 16 -> 64 -> 64 -> 3
 constexpr int kNParam = kNH * kNF + kNH + kNH * kNH + kNH + kNO * kNH + kNO;  // 5443
@@ -51,6 +52,12 @@ struct DevSystem {
     const double2* e_val;
     const double* f_diag;      // [12 + n_c][d]: rows 0..11 diagonal feature operators (learned form),
                                // rows 12 + n: diagonal of C_n^dag C_n when c_isdiag
+    // time-dependent terms (small dense kernel): M(t) = M + sum_k f_k(t) (-i H_k) with
+    // f_k(t) = td[4k] + td[4k+1] cos(td[4k+3] t) + td[4k+2] sin(td[4k+3] t)
+    int n_td;
+    const double* td;          // [n_td][4] coefficients (c, a, b, w)
+    const double* Mtd;         // [n_td][(2dp)^2] team-layout A-fragments of -i H_k
+    const float* Mtd32;        // same, rounded to FP32
     int c_isdiag;              // every C_n has at most one entry per row, so C_n^dag C_n is diagonal
     int tile_band;             // team layout: every 16-row tile (rt, s) holding a nonzero has |rt - s| <= 1
     const double2* psi0;       // [d]
@@ -81,7 +88,8 @@ struct RunArgs {
     const float* mlp;          // [kNTotal] weights (BF16-rounded values), biases, mean, scale
     const unsigned short* mlpf;  // [kMlpFrag] BF16 weight fragments for the matrix-core evaluation
     long long* fail;           // smallest failing global trajectory index (LLONG_MAX: none)
-    unsigned long long* counters;  // [4]: product passes (sum over teams), unused, most passes of one team, unused
+    unsigned long long* counters;  // [4]: product passes (sum over teams), norm-polynomial evaluations of
+                                   // the jump-time root finds, most passes of one team, unused
     long long max_cycles;      // failsafe bound on block cycles
     int tile_cols;             // requested columns per block (0: as many as the waves allow)
     int persistent;            // refill free slots from the queue

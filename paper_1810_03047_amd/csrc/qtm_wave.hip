@@ -60,8 +60,10 @@ __device__ __forceinline__ constexpr double dense_coef(int a, int i) {
 }
 
 // LEARN = false compiles out the segment-start features and the proposal network
-// (kernels that never run the learned form or record segments).
-template <int T, int NWT, int PREC, bool LEARN = true, int BAND = 0>
+// (kernels that never run the learned form or record segments).  TD = true adds the
+// time-dependent terms of the Hamiltonian: every product is M W + sum_k M_k (f_k(t_s) W)
+// with each lane's own stage time t_s.
+template <int T, int NWT, int PREC, bool LEARN = true, int BAND = 0, bool TD = false>
 struct Team {
     typedef typename MfmaT<PREC>::in_t in_t;
     typedef typename std::conditional<PREC == 0, double2, float2>::type kv_t;   // stage vectors
@@ -70,6 +72,8 @@ struct Team {
     const DevSystem& S;
     const RunArgs& A;
     const in_t* Mf;          // LDS: A-fragments [RT][RT][64][4] (output tile, source tile, lane, slot)
+    const in_t* Mt;          // TD: A-fragments of the time-dependent terms [n_td][RT][RT][64][4]
+                             // (LDS, or global memory when they do not fit)
     in_t* Wb;                // LDS: operand tiles [RT][64][4] (teams of several waves)
     double2* St;             // alias of Wb: complex staging [dp][16]
     double* Xb;              // LDS: team reduction exchange [NWT][16][kXV]
@@ -83,6 +87,7 @@ struct Team {
 
     // per-lane trajectory state (identical on every lane of a column, on every wave)
     double t, h, h0, d1, r, u, tseg, tb, fac, th, oth, tnext, tnext2;   // output times k, k + 1
+    double tstage;           // TD: time at which the next product evaluates the right-hand side
     long long traj;
     int state, action, seg, kk, nacc, nrej, njump, natt, last, rejected, omode, ch, seg_rec, first_acc;
     bool exhausted;
@@ -198,6 +203,26 @@ struct Team {
                         if (in_band(tt, s)) acc[tt] = MfmaT<PREC>::op(av[tt].v[i], b.v[i], acc[tt]);
                 __builtin_amdgcn_sched_barrier(0);     // one source tile of fragments in flight at a time
             }
+            if constexpr (TD) {
+                // + M_k (f_k(t_s) W): the scale is the lane's own (its trajectory's) coefficient
+                for (int q = 0; q < S.n_td; ++q) {
+                    const in_t f = (in_t)td_coef(q);
+                    const in_t* Mq = Mt + (size_t)q * RT * RT * 256;
+#pragma unroll
+                    for (int s = 0; s < T; ++s) {
+                        In4 b = slots(W[2 * s], W[2 * s + 1]);
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) b.v[i] *= f;
+                        In4 av[T];
+#pragma unroll
+                        for (int tt = 0; tt < T; ++tt) av[tt] = *(const In4*)(Mq + ((size_t)(tt * T + s) * 64 + lane) * 4);
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+#pragma unroll
+                            for (int tt = 0; tt < T; ++tt) acc[tt] = MfmaT<PREC>::op(av[tt].v[i], b.v[i], acc[tt]);
+                    }
+                }
+            }
         } else {
             team_sync();                // earlier readers of the operand tiles are done
 #pragma unroll
@@ -223,6 +248,25 @@ struct Team {
 #pragma unroll
                     for (int tt = 0; tt < T; ++tt) acc[tt] = MfmaT<PREC>::op(av[tt].v[i], b.v[i], acc[tt]);
             }
+            if constexpr (TD) {
+                // + M_k (f_k(t_s) W); the staged tile a lane reads holds its own trajectory
+                for (int q = 0; q < S.n_td; ++q) {
+                    const in_t f = (in_t)td_coef(q);
+                    const size_t qo = (size_t)q * RT * RT * 256;
+                    for (int s = 0; s < RT; ++s) {
+                        In4 b = *(const In4*)(Wb + ((size_t)s * 64 + lane) * 4);
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) b.v[i] *= f;
+                        In4 av[T];
+#pragma unroll
+                        for (int tt = 0; tt < T; ++tt) av[tt] = *(const In4*)(Mt + qo + (ap[tt] - Mf) + (size_t)s * 256);
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+#pragma unroll
+                            for (int tt = 0; tt < T; ++tt) acc[tt] = MfmaT<PREC>::op(av[tt].v[i], b.v[i], acc[tt]);
+                    }
+                }
+            }
         }
 #pragma unroll
         for (int tt = 0; tt < T; ++tt) {
@@ -230,6 +274,14 @@ struct Team {
             K[2 * tt + 1] = from_d2<kv_t>(make_double2((double)acc[tt][2], (double)acc[tt][3]));
         }
         ++passes;       // summed into the run counters once, when the team exits
+    }
+
+    // f_q(tstage) = c + a cos(w t) + b sin(w t) of time-dependent term q (FP64, this lane's time)
+    QTM_DI double td_coef(int q) const {
+        const double* c = S.td + 4 * q;
+        double sn, cs;
+        sincos(c[3] * tstage, &sn, &cs);
+        return c[0] + c[1] * cs + c[2] * sn;
     }
 
     // ------------------------------------------------------------ dense output
@@ -529,6 +581,7 @@ struct Team {
     // k1 = M y, then the starting step (or the learned proposal)
     QTM_DI void segment_start() {
         kv_t K[NE];
+        if constexpr (TD) tstage = t;
         product(y, K);
 #pragma unroll
         for (int e = 0; e < NE; ++e)
@@ -771,6 +824,11 @@ struct Team {
             } else {
                 w[e] = from_d2<kv_t>(acc);
             }
+        }
+        if constexpr (TD) {
+            // stage s of a step at t + c_s h; the starting step's probe (stage 1 of a
+            // segment start) at t + h0
+            tstage = state == ST_STEP ? t + dp_c(s) * h : (s == 1 && state == ST_NEEDF1) ? t + h0 : t;
         }
         if constexpr (s == 6) product(yn, k[s]);
         else product(w, k[s]);
@@ -1049,15 +1107,17 @@ struct Team {
     }
 };
 
-// LDS of a block: [A-fragments of M][per team: operand tile, team exchange, hand-out, flags]
-// [diagonal observables][FP32 feature table].  Blocks of single-wave teams hold TPB teams
-// that share M and never meet at a barrier after the set-up.
+// LDS of a block: [A-fragments of M][A-fragments of the ntd time-dependent terms kept in
+// LDS][per team: operand tile, team exchange, hand-out, flags][diagonal observables][FP32
+// feature table].  Blocks of single-wave teams hold TPB teams that share M and never meet
+// at a barrier after the set-up.
 struct TeamLds { size_t m, team, w, x, ib, fb, od, ft, total; };
-static __host__ __device__ TeamLds team_lds(int dp, int d, int n_e, int prec, int nwt, int tpb, int od_lds) {
+static __host__ __device__ TeamLds team_lds(int dp, int d, int n_e, int prec, int nwt, int tpb, int od_lds,
+                                            int ntd = 0) {
     TeamLds L;
     size_t es = prec == 0 ? 8 : 4;
     L.m = 0;
-    L.w = (((size_t)(2 * dp) * (2 * dp) * es) + 15) & ~(size_t)15;       // first team's tile
+    L.w = (((size_t)(1 + ntd) * (2 * dp) * (2 * dp) * es) + 15) & ~(size_t)15;   // first team's tile
     L.x = (size_t)2 * dp * 16 * sizeof(double);                             // offsets inside a team
     L.ib = L.x + (size_t)nwt * 16 * kXV * sizeof(double);
     L.fb = L.ib + 16 * sizeof(unsigned long long);
@@ -1068,17 +1128,24 @@ static __host__ __device__ TeamLds team_lds(int dp, int d, int n_e, int prec, in
     return L;
 }
 
-template <int T, int NWT, int PREC, int BAND = 0>
-__global__ void __launch_bounds__(NWT == 1 ? 256 : 64 * NWT) traj_team_kernel(RunArgs a, int od_lds, int tpb) {
+// td_lds (TD instances): the time-dependent terms' fragments are copied into LDS after M
+// (otherwise read from global memory)
+template <int T, int NWT, int PREC, int BAND = 0, bool TD = false>
+__global__ void __launch_bounds__(NWT == 1 ? 256 : 64 * NWT) traj_team_kernel(RunArgs a, int od_lds, int tpb, int td_lds) {
     typedef typename MfmaT<PREC>::in_t in_t;
     extern __shared__ double smem[];
     const DevSystem& S = a.sys[0];
-    const TeamLds L = team_lds(S.dp, S.d, S.n_e, PREC, NWT, tpb, od_lds);
+    const int ntd_lds = (TD && td_lds) ? S.n_td : 0;
+    const TeamLds L = team_lds(S.dp, S.d, S.n_e, PREC, NWT, tpb, od_lds, ntd_lds);
     char* base = (char*)smem;
     const in_t* Mg = MfmaT<PREC>::frag(S);
     in_t* Ml = (in_t*)(base + L.m);
     const size_t nm = (size_t)(2 * S.dp) * (2 * S.dp);
     for (size_t i = threadIdx.x; i < nm; i += blockDim.x) Ml[i] = Mg[i];
+    if constexpr (TD) {
+        const in_t* Tg = MfmaT<PREC>::td(S);
+        for (size_t i = threadIdx.x; i < (size_t)ntd_lds * nm; i += blockDim.x) Ml[nm + i] = Tg[i];
+    }
     double2* Odl = (double2*)(base + L.od);
     if (od_lds)
         for (int o = 0; o < S.n_e; ++o)
@@ -1094,8 +1161,9 @@ __global__ void __launch_bounds__(NWT == 1 ? 256 : 64 * NWT) traj_team_kernel(Ru
     __syncthreads();
     const int team = (threadIdx.x >> 6) / NWT;
     char* tb = base + L.w + (size_t)team * L.team;
-    Team<T, NWT, PREC, true, BAND> W(S, a);
+    Team<T, NWT, PREC, true, BAND, TD> W(S, a);
     W.Mf = Ml;
+    W.Mt = ntd_lds ? (const in_t*)(Ml + nm) : MfmaT<PREC>::td(S);
     W.Wb = (in_t*)tb;
     W.St = (double2*)tb;
     W.Xb = (double*)(tb + L.x);
@@ -1177,6 +1245,7 @@ __global__ void __launch_bounds__(64 * NWT) traj_team_batch_kernel(RunArgs a, in
         __syncthreads();
         Team<T, NWT, PREC, false> W(S, a);
         W.Mf = MfmaT<PREC>::team(S);
+        W.Mt = nullptr;
         W.Wb = (in_t*)(base + L.w);
         W.St = (double2*)(base + L.w);
         W.Xb = (double*)(base + L.x);
@@ -1210,6 +1279,7 @@ __global__ void __launch_bounds__(64 * NWT) traj_team_batch_kernel(RunArgs a, in
 // compile in parallel; each defines QTM_WAVE_INSTANCES.
 template <int T, int NWT, int PREC> const void* team_fn_inst();
 template <int T, int PREC> const void* team_fn_band_inst();   // single-wave teams, banded operator
+template <int T, int NWT, int PREC> const void* team_fn_td_inst();   // default shapes, time-dependent terms
 
 // Team shapes (T row tiles per wave, NWT waves per team) compiled for each number
 // of 16-row tiles RT = 2 dp / 16; the first entry of a row is the default.
@@ -1262,11 +1332,21 @@ int wave_supported(int d) {
 }
 
 // LDS of a team-kernel block for one shape; tpb reduced until it fits (0 if it never does)
-static size_t team_block_lds(int dp, const DevSystem& s0, int prec, int nwt, int od_lds, int* tpb) {
+static size_t team_block_lds(int dp, const DevSystem& s0, int prec, int nwt, int od_lds, int* tpb, int ntd = 0) {
     *tpb = nwt == 1 ? 4 : 1;
-    TeamLds L = team_lds(dp, s0.d, s0.n_e, prec, nwt, *tpb, od_lds);
-    while (*tpb > 1 && L.total > 160 * 1024) L = team_lds(dp, s0.d, s0.n_e, prec, nwt, --*tpb, od_lds);
+    TeamLds L = team_lds(dp, s0.d, s0.n_e, prec, nwt, *tpb, od_lds, ntd);
+    while (*tpb > 1 && L.total > 160 * 1024) L = team_lds(dp, s0.d, s0.n_e, prec, nwt, --*tpb, od_lds, ntd);
     return L.total > 160 * 1024 ? 0 : L.total;
+}
+
+// The time-dependent instance of the default shape for RT tiles (see kShapes)
+static const void* team_fn_td(int T, int nwt, int prec) {
+#define QTM_TD_CASE(TT, NN) \
+    if (T == TT && nwt == NN) return prec == 0 ? team_fn_td_inst<TT, NN, 0>() : team_fn_td_inst<TT, NN, 1>();
+    QTM_TD_CASE(1, 1) QTM_TD_CASE(2, 1) QTM_TD_CASE(3, 1) QTM_TD_CASE(4, 1) QTM_TD_CASE(5, 1)
+    QTM_TD_CASE(3, 2) QTM_TD_CASE(4, 2) QTM_TD_CASE(2, 4)
+#undef QTM_TD_CASE
+    return nullptr;
 }
 
 int launch_wave(const RunArgs& a, const DevSystem& s0, int prec, int waves_per_team, hipStream_t st, LaunchInfo* info) {
@@ -1279,6 +1359,38 @@ int launch_wave(const RunArgs& a, const DevSystem& s0, int prec, int waves_per_t
     // single-wave teams: up to 4 per block, sharing the operator in LDS; a shape whose
     // block does not fit the 160 KB of LDS gives way to the next shape of the same tile count
     int tpb = 1;
+    if (s0.n_td > 0) {
+        // time-dependent terms: the default shape only; their fragments in LDS when they fit
+        int T0, n0;
+        team_shape(rt, 0, &T0, &n0);
+        if (waves_per_team != 0 && waves_per_team != n0) return -1;
+        T = T0; nwt = n0;
+        int td_lds = 1;
+        size_t ltd = team_block_lds(dp, s0, prec, nwt, od_lds, &tpb, s0.n_td);
+        if (ltd == 0) { td_lds = 0; ltd = team_block_lds(dp, s0, prec, nwt, od_lds, &tpb); }
+        if (ltd == 0 && od_lds) { od_lds = 0; ltd = team_block_lds(dp, s0, prec, nwt, od_lds, &tpb); }
+        if (ltd == 0) return -2;
+        const void* fn = team_fn_td(T, nwt, prec);
+        if (!fn) return -1;
+        if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)ltd) != hipSuccess) return -3;
+        int dev = 0, ncu = 0, nb = 1;
+        const int threads = nwt * tpb * 64;
+        if (hipGetDevice(&dev) != hipSuccess) return -3;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return -3;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, threads, ltd) != hipSuccess || nb < 1) nb = 1;
+        const int cols = 16 * tpb;
+        long long need = (s0.count + cols - 1) / cols;
+        long long blocks = a.persistent ? (long long)ncu * nb : need;
+        if (blocks > need) blocks = need;
+        if (blocks < 1) blocks = 1;
+        void* args[] = {(void*)&a, (void*)&od_lds, (void*)&tpb, (void*)&td_lds};
+        if (hipLaunchKernel(fn, dim3((unsigned)blocks), dim3(threads), args, ltd, st) != hipSuccess) return -3;
+        if (info) {
+            info->blocks = (int)blocks; info->threads = threads; info->lds = (int)ltd; info->cols = cols;
+            info->shape = T * 100 + nwt;
+        }
+        return hipGetLastError() == hipSuccess ? 0 : -3;
+    }
     size_t lds = team_block_lds(dp, s0, prec, nwt, od_lds, &tpb);
     for (int i = 0; i < 3 && lds == 0 && waves_per_team == 0; ++i) {
         T = kShapes[rt][i][0]; nwt = kShapes[rt][i][1];
@@ -1312,7 +1424,8 @@ int launch_wave(const RunArgs& a, const DevSystem& s0, int prec, int waves_per_t
     long long blocks = a.persistent ? (long long)ncu * nb : need;
     if (blocks > need) blocks = need;
     if (blocks < 1) blocks = 1;
-    void* args[] = {(void*)&a, (void*)&od_lds, (void*)&tpb};
+    int td_lds = 0;
+    void* args[] = {(void*)&a, (void*)&od_lds, (void*)&tpb, (void*)&td_lds};
     if (hipLaunchKernel(fn, dim3((unsigned)blocks), dim3(threads), args, L.total, st) != hipSuccess) return -3;
     const bool band = nwt == 1 && s0.tile_band && (T == 4 || T == 5);
     if (info) {
