@@ -90,8 +90,21 @@ typedef struct {
     int32_t tile_cols;        /* sparse and large dense kernels: trajectories per workgroup (0: default) */
     int32_t team_waves;       /* small dense kernel (d <= 64): wavefronts per 16-trajectory team,
                                  one of qtm_tile_candidates() (0: default shape) */
-    int32_t reserved[6];
+    int32_t integrator;       /* QTM_INT_DOPRI5 (default) or QTM_INT_EXPO */
+    int32_t expo_substeps;    /* QTM_INT_EXPO: propagator steps per output interval (0: 1) */
+    int32_t reserved[4];
 } qtm_opts;
+
+/* Integrators.  QTM_INT_DOPRI5: adaptive Dormand-Prince 5(4) with dense output (the
+ * default; every form).  QTM_INT_EXPO: the exact propagator for stiff problems --
+ * between jumps psi(t + h) = exp(h M) psi(t) with exp(h M) computed once on the host,
+ * one product per step whatever the stiffness of M (the role the paper gives its
+ * BDF option, Sec. 2.1 and Sec. 3); the jump time is found by a binary search with
+ * the exact propagators exp(h 2^-j M) to h 2^-J <= about 1e-12.  Requirements:
+ * time-independent H (qtm_create), FP64 products, the plain or batched form, d <= 40,
+ * output times uniformly spaced (steps of h = spacing / expo_substeps). */
+#define QTM_INT_DOPRI5 0
+#define QTM_INT_EXPO   1
 
 /* Per-run statistics (summed over trajectories of the last qtm_run). */
 typedef struct {

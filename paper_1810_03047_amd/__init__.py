@@ -24,6 +24,7 @@ LIB_PATH = os.path.join(_HERE, "libqtm.so")
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_STEP, E_STATE = 0, -1, -2, -3, -4, -5
 PREC_FP64, PREC_FP32 = 0, 1
 FORM_LEARNED, FORM_BATCHED = 1, 2
+INT_DOPRI5, INT_EXPO = 0, 1       # integrators: adaptive Dormand-Prince 5(4); exact propagator (stiff)
 MLP_NPARAM, MLP_NTOTAL = 5443, 5475
 SEG_REC = 20
 NOALLOC_SCRATCH_MB = 32          # QTM_NOALLOC_SCRATCH_MB of include/qtm.h
@@ -49,7 +50,8 @@ class _Opts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("precision", C.c_int32), ("form", C.c_uint32),
                 ("max_steps", C.c_int64), ("device", C.c_int32), ("record_jumps", C.c_int32),
                 ("stream", C.c_void_p), ("keep_traj", C.c_int32), ("seg_cap", C.c_int32),
-                ("tile_cols", C.c_int32), ("team_waves", C.c_int32), ("reserved", C.c_int32 * 6)]
+                ("tile_cols", C.c_int32), ("team_waves", C.c_int32), ("integrator", C.c_int32),
+                ("expo_substeps", C.c_int32), ("reserved", C.c_int32 * 4)]
 
 
 class _Stats(C.Structure):
@@ -179,6 +181,8 @@ class Opts:
     seg_cap: int = 0
     tile_cols: int = 0
     team_waves: int = 0
+    integrator: int = INT_DOPRI5
+    expo_substeps: int = 0
     stream: Optional[int] = None      # raw hipStream_t; None: torch's current stream when available
 
     def _c(self) -> _Opts:
@@ -188,6 +192,7 @@ class Opts:
         o.max_steps, o.device, o.record_jumps = self.max_steps, self.device, self.record_jumps
         o.keep_traj, o.seg_cap, o.tile_cols = self.keep_traj, self.seg_cap, self.tile_cols
         o.team_waves = self.team_waves
+        o.integrator, o.expo_substeps = self.integrator, self.expo_substeps
         st = self.stream
         if st is None:
             try:

@@ -20,7 +20,7 @@ OBJDIR = os.path.join(HERE, "_build")
 ARCH = "gfx950"
 # team-kernel shapes (row tiles per wave x waves per team), one translation unit each
 TEAM_SHAPES = ("1x1", "2x1", "1x2", "1x3", "1x4", "2x2", "1x5", "3x2", "5x1", "1x6", "2x3", "1x7", "4x2", "1x8", "2x4", "3x1", "4x1")
-EXTRA = ["qtm_wave_batch.hip", "qtm_wave_td0.hip", "qtm_wave_td1.hip", "qtm_sparse_r1.hip", "qtm_sparse_r2.hip", "qtm_sparse_r4.hip"]
+EXTRA = ["qtm_wave_batch.hip", "qtm_wave_td0.hip", "qtm_wave_td1.hip", "qtm_expo.hip", "qtm_sparse_r1.hip", "qtm_sparse_r2.hip", "qtm_sparse_r4.hip"]
 SOURCES = ["qtm_wave.hip"] + [f"qtm_wave_t{s}.hip" for s in TEAM_SHAPES] + EXTRA + ["qtm_dense.hip", "qtm_sparse.hip",
                                                                      "qtm_mlp.hip", "qtm_capi.cpp"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -217,6 +217,12 @@ struct DevBuf {
 
 struct SysHost {
     int d = 0, n_c = 0, n_e = 0, n_t = 0, n_f = 0;
+    // exact-propagator integrator: fragments of exp(h 2^-j M), j = 0..expo_J (device)
+    bool expo = false;
+    const double* expo_P = nullptr;
+    int expo_J = 0, expo_m = 1;
+    double expo_h = 0.0;
+    long long expo_NS = 0;
     bool sparse = false;       // sliced-ELL kernel (CSR H, or dense H with d > 128)
     bool team = false;         // team kernel (dense, d <= 64); otherwise the block dense kernel
     qtm::DevSystem dev{};
@@ -305,6 +311,42 @@ int ensure_buf(DevBuf& b, size_t bytes) {
     return QTM_OK;
 }
 
+// exp(A) of a dense complex d x d matrix (row-major) by scaling and squaring: A / 2^s has
+// infinity norm at most 1/4, where the degree-18 Taylor polynomial leaves a truncation
+// error below (1/4)^19 / 19! (about 2e-29 relative), then s squarings.
+std::vector<cd> expm_dense(const std::vector<cd>& A, int d) {
+    double nrm = 0.0;
+    for (int i = 0; i < d; ++i) {
+        double rs = 0.0;
+        for (int j = 0; j < d; ++j) rs += std::abs(A[(size_t)i * d + j]);
+        nrm = std::max(nrm, rs);
+    }
+    int sq = 0;
+    while (nrm > 0.25 && sq < 1000) { nrm *= 0.5; ++sq; }
+    const double sc = std::ldexp(1.0, -sq);
+    std::vector<cd> B(A.size()), E((size_t)d * d, 0.0), term((size_t)d * d, 0.0), tmp((size_t)d * d);
+    for (size_t i = 0; i < A.size(); ++i) B[i] = A[i] * sc;
+    for (int i = 0; i < d; ++i) { E[(size_t)i * d + i] = 1.0; term[(size_t)i * d + i] = 1.0; }
+    auto mul = [&](const std::vector<cd>& X, const std::vector<cd>& Y, std::vector<cd>& Z) {
+        for (int i = 0; i < d; ++i)
+            for (int j = 0; j < d; ++j) {
+                cd acc = 0.0;
+                for (int l = 0; l < d; ++l) acc += X[(size_t)i * d + l] * Y[(size_t)l * d + j];
+                Z[(size_t)i * d + j] = acc;
+            }
+    };
+    for (int kx = 1; kx <= 18; ++kx) {
+        mul(term, B, tmp);
+        for (size_t i = 0; i < tmp.size(); ++i) term[i] = tmp[i] / (double)kx;
+        for (size_t i = 0; i < E.size(); ++i) E[i] += term[i];
+    }
+    for (int q = 0; q < sq; ++q) {
+        mul(E, E, tmp);
+        E.swap(tmp);
+    }
+    return E;
+}
+
 // Time-dependent terms of one system (qtm_create_td).
 struct TdSpec {
     const qtm_op* H = nullptr;
@@ -342,6 +384,10 @@ int setup_system(SysHost& S, const qtm_system& in, int idx, const qtm_opts& o, b
     // MFMA block kernel (d <= 128), or the SpMM kernel on full rows (d <= 2048)
     S.sparse = H->fmt == QTM_FMT_CSR || d > 128;
     S.team = !S.sparse && qtm::wave_supported(d);
+    if (o.integrator == QTM_INT_EXPO && d <= 40) {
+        S.sparse = false;                   // the exact-propagator kernel uses the team layout
+        S.team = true;
+    }
     const int n_td = td ? td->n : 0;
     if (n_td) {
         if (n_td < 0 || n_td > QTM_MAX_TD) return fail(QTM_E_INVAL, "n_td = %d outside [1, %d]", n_td, QTM_MAX_TD);
@@ -417,6 +463,47 @@ int setup_system(SysHost& S, const qtm_system& in, int idx, const qtm_opts& o, b
             if ((rc = upload(S, &D.Mteam, build_frag_team<double>(M, dp, 0)))) return rc;
             if ((rc = upload(S, &D.Mteam32, build_frag_team<float>(M, dp, 1)))) return rc;
         }
+    }
+    if (o.integrator == QTM_INT_EXPO) {
+        // exact propagator: uniform output grid, h = spacing / substeps, fragments of
+        // exp(h 2^-j M) for j = 0..J with h 2^-J of about 1e-12
+        if (n_td) return fail(QTM_E_INVAL, "the exact-propagator integrator needs a time-independent H");
+        if (d > 40) return fail(QTM_E_INVAL, "the exact-propagator integrator supports d <= 40; d = %d", d);
+        const double span = in.tlist[in.n_t - 1] - in.tlist[0], dt = span / (in.n_t - 1);
+        for (int k = 0; k + 1 < in.n_t; ++k)
+            if (std::fabs((in.tlist[k + 1] - in.tlist[k]) - dt) > 1e-9 * dt)
+                return fail(QTM_E_INVAL, "the exact-propagator integrator needs uniformly spaced output times");
+        const int m = std::max(1, (int)o.expo_substeps);
+        const double h = dt / m;
+        int J = (int)std::ceil(std::log2(h / 1e-12));
+        J = std::min(52, std::max(8, J));
+        const int dp = S.dev.dp, n = 2 * dp;
+        std::vector<cd> Md((size_t)d * d, 0.0);
+        for (int i = 0; i < d; ++i)
+            for (int p = M.rp[i]; p < M.rp[i + 1]; ++p) Md[(size_t)i * d + M.ci[p]] += M.v[p];
+        std::vector<double> frags;
+        frags.reserve((size_t)(J + 1) * n * n);
+        for (int j = 0; j <= J; ++j) {
+            std::vector<cd> A(Md.size());
+            const double tau = std::ldexp(h, -j);
+            for (size_t i = 0; i < Md.size(); ++i) A[i] = tau * Md[i];
+            const std::vector<cd> P = expm_dense(A, d);
+            HCsr Pc;
+            Pc.d = d;
+            Pc.rp.assign(d + 1, 0);
+            for (int i = 0; i < d; ++i) {
+                for (int c = 0; c < d; ++c) { Pc.ci.push_back(c); Pc.v.push_back(P[(size_t)i * d + c]); }
+                Pc.rp[i + 1] = (int)Pc.ci.size();
+            }
+            const std::vector<double> f = build_frag_team<double>(Pc, dp, 0);
+            frags.insert(frags.end(), f.begin(), f.end());
+        }
+        if ((rc = upload(S, &S.expo_P, frags))) return rc;
+        S.expo = true;
+        S.expo_J = J;
+        S.expo_m = m;
+        S.expo_h = h;
+        S.expo_NS = (long long)(in.n_t - 1) * m;
     }
     // sliced ELL: for the SpMM kernel, and for every system of a batch (the single
     // launch over all systems runs on it)
@@ -717,6 +804,14 @@ static int create_common(qtm_ctx** out, int32_t n_sys, const qtm_system* sys, co
     if (opt.max_steps < 1) return fail(QTM_E_INVAL, "max_steps must be >= 1");
     if (opt.record_jumps < 0 || opt.seg_cap < 0) return fail(QTM_E_INVAL, "negative capacity");
     if (opt.team_waves < 0 || opt.tile_cols < 0) return fail(QTM_E_INVAL, "negative tile option");
+    if (opt.integrator != QTM_INT_DOPRI5 && opt.integrator != QTM_INT_EXPO) return fail(QTM_E_INVAL, "unknown integrator %d", opt.integrator);
+    if (opt.integrator == QTM_INT_EXPO) {
+        if (opt.precision != QTM_PREC_FP64) return fail(QTM_E_INVAL, "the exact-propagator integrator uses FP64 products");
+        if ((opt.form & QTM_FORM_LEARNED) || opt.seg_cap > 0)
+            return fail(QTM_E_INVAL, "the exact-propagator integrator has no step proposal");
+        if (batch) return fail(QTM_E_INVAL, "the exact-propagator integrator takes one system (qtm_create)");
+        if (opt.expo_substeps < 0) return fail(QTM_E_INVAL, "negative expo_substeps");
+    }
     int ndev = 0;
     hipError_t de = hipGetDeviceCount(&ndev);
     if (de != hipSuccess || ndev < 1) return fail(QTM_E_DEVICE, "no HIP device (%s, count %d)", hipGetErrorString(de), ndev);
@@ -886,7 +981,9 @@ static int enqueue_run(qtm_ctx* c, const qtm::RunArgs& a, long long count, hipSt
             as.n_sys = 1;
             int lr;
             qtm::LaunchInfo lx{};
-            if (Sx.sparse) {
+            if (Sx.expo) {
+                lr = qtm::launch_expo(as, Sx.dev, Sx.expo_P, Sx.expo_J, Sx.expo_m, Sx.expo_h, Sx.expo_NS, ss, &lx);
+            } else if (Sx.sparse) {
                 int cols = c->o.tile_cols > 0 ? c->o.tile_cols : (c->o.precision == QTM_PREC_FP32 ? 4 : 2);
                 lr = qtm::launch_sparse(as, Sx.dev, Sx.d, Sx.dev.ell_n, c->o.precision, cols, ss, &lx);
             } else if (Sx.team) {

@@ -128,5 +128,9 @@ int team_candidates(int d, int* waves, int cap);
 // a.sys holds the class's systems; returns -1 when max_d > 256
 int launch_team_batch(const RunArgs& a, int max_d, int max_ne, int prec, hipStream_t st, LaunchInfo* info);
 int team_batch_class(int d);      // 0, 1, 2 for d <= 64, 128, 256; -1 above
+// exact-propagator kernel (qtm_expo.hip), d <= 40, FP64: Pg = fragments of exp(h 2^-j M),
+// j = 0..J; m steps per output interval, NS steps from t0 to t_end
+int launch_expo(const RunArgs& a, const DevSystem& s0, const double* Pg, int J, int m, double h, long long NS,
+                hipStream_t st, LaunchInfo* info);
 
 }  // namespace qtm
