@@ -11,8 +11,9 @@ The line also nests, under "secondary", the same measurement (plain FP64 form
 against the batched FP32 form, roofline, CPU baseline and oracle check) for the
 driven two-level atom (500 trajectories), the transverse-field Ising chain
 (L = 10, d = 1024, CSR, 20,000 trajectories), the heterogeneous batch (64
-systems, d 8..256, 500 trajectories each) and the paper's trilinear Hamiltonian
-(d = 512, CSR, 20,000 trajectories).
+systems, d 8..256, 500 trajectories each), the paper's trilinear Hamiltonian
+(d = 512, CSR, 20,000 trajectories), and a stiff Jaynes-Cummings cavity (decay 40,
+10,000 trajectories: adaptive DOPRI5 against the exact-propagator form).
 
 Forms: "plain" (FP64 products, the starting-step rule at every segment start)
 and the headline "learned+batched+mixed" (FP32 products with FP64 state,
@@ -33,7 +34,7 @@ run are reported beside it as run_event_ms (that span also holds the output
 clearing, the averaging and the read-back of the sums).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--forms plain,best] [--no-secondary]
-    python bench.py --workload two_level|tfim|hetero|trilinear     (one configuration alone)
+    python bench.py --workload two_level|tfim|hetero|trilinear|stiff     (one configuration alone)
 """
 import argparse
 import json
@@ -309,6 +310,15 @@ def secondary_spec(name, qtm, w):
                     fps=[6 * 8.0 * nnz + 128.0 * s[0].dim], check_n=20_000,
                     label=f"trilinear (Sec. 4.2) cutoff 8 per mode (d=512, CSR, nnz(M) {nnz}), K=1, "
                           "gamma=(0.1,0.1,0.4), alpha=sqrt(3), t in [0,4] (100 points), 20000 trajectories")
+    if name == "stiff":
+        s = [w.jaynes_cummings(kappa=40.0, t_end=10.0, n_t=101)]
+        d = s[0].dim
+        return dict(systems=s, n=10_000, batch=False, kernel="traj_expo_kernel", bound="mfma", peak=PEAK["fp64"],
+                    fps=None, flop_per_pass=16 * 8.0 * d * d, check_n=200,
+                    forms=(("plain", dict(precision=0, form=2)), ("best", dict(precision=0, form=2, integrator=1))),
+                    label="stiff Jaynes-Cummings N=20 x atom (d=40, dense), g=1, cavity decay 40, atomic decay 0.05, "
+                          "alpha=2, t in [0,10] (101 points), 10000 trajectories; adaptive DOPRI5 (FP64, batched) "
+                          "against the exact propagator (FP64, batched)")
     if name == "hetero":
         s = w.hetero_batch()
         return dict(systems=s, n=500, batch=True, kernel="traj_team_batch_kernel (three tile classes)", bound="mfma",
@@ -326,8 +336,10 @@ def run_secondary(name, qtm, w, torch, steps, warmup, cpu=True):
     total = n * len(systems)
     make = (lambda o: qtm.create_batch(systems, o)) if sp["batch"] else (lambda o: qtm.create_system(systems[0], o))
     out = {}
-    for form_name, o in (("plain", qtm.Opts(precision=qtm.PREC_FP64)),
-                         ("best", qtm.Opts(precision=qtm.PREC_FP32, form=qtm.FORM_BATCHED))):
+    forms = sp.get("forms", (("plain", dict(precision=qtm.PREC_FP64)),
+                             ("best", dict(precision=qtm.PREC_FP32, form=qtm.FORM_BATCHED))))
+    for form_name, kw in forms:
+        o = qtm.Opts(**kw)
         ctx = make(o)
         for i in range(warmup):
             ctx.run(n, 1000 + i)
@@ -351,6 +363,9 @@ def run_secondary(name, qtm, w, torch, steps, warmup, cpu=True):
                  traj_steps_per_launch=units / steps)
         if fl:
             r["tflops"] = float(np.mean(fl)) / (float(np.mean(kms)) * 1e-3) / 1e12
+        elif sp.get("flop_per_pass") and o.integrator == qtm.INT_EXPO:
+            r["tflops"] = st["passes"] * sp["flop_per_pass"] / (float(np.mean(kms)) * 1e-3) / 1e12
+            r["products_per_team"] = st["passes"] / max(1, -(-n // 16))
         else:
             r["kernel_us_per_team_pass"] = 1e3 * float(np.mean(kms)) / max(1, st["max_team_passes"])
         out[form_name] = r
@@ -363,7 +378,10 @@ def run_secondary(name, qtm, w, torch, steps, warmup, cpu=True):
         "config": {"workload": sp["label"], "ntraj": total, "form": "batched+mixed", "parallelism": "trajectories (1 GPU)"},
         "plain": out["plain"], "speedup_vs_plain": b["value"] / out["plain"]["value"],
     }
-    if sp["peak"] is not None:
+    if name == "stiff":
+        line["dtype"] = "f64"
+        line["config"]["form"] = "exact propagator (batched)"
+    if sp["peak"] is not None and "tflops" in b:
         line["roofline"] = {"bound": sp["bound"], "achieved": b["tflops"], "peak": sp["peak"], "unit": "TFLOP/s",
                             "frac": b["tflops"] / sp["peak"], "traffic": None, "kernel": sp["kernel"],
                             "kernel_ms": b["kernel_ms"]}
@@ -371,7 +389,9 @@ def run_secondary(name, qtm, w, torch, steps, warmup, cpu=True):
         line["roofline"] = None
         line["latency"] = {"kernel": sp["kernel"], "kernel_ms": b["kernel_ms"],
                            "us_per_team_pass": b["kernel_us_per_team_pass"]}
-    if cpu:
+    if cpu and name == "stiff":
+        line["cpu_baseline"], line["oracle_check"] = stiff_cpu_leg(qtm, systems[0], sp["check_n"])
+    elif cpu:
         line["cpu_baseline"] = cpu_baseline_systems(systems, n)
         # the oracle on the first trajectories of timed seed 0 of every system, against the
         # batched FP32 form on the same trajectories
@@ -422,6 +442,33 @@ def oracle_check_systems(qtm, systems, batch, m):
             "identical_jump_counts": same / tot}
 
 
+def stiff_cpu_leg(qtm, system, m):
+    """The exact-propagator oracle (Python, scipy's matrix exponential, one thread) timed on
+    trajectories 0..m-1 of seed 0, and the same trajectories of the library's
+    exact-propagator form compared with it one by one."""
+    from oracle import expo
+    t0 = time.perf_counter()
+    r = expo.run_expo(system, m, seed=0)
+    dt = time.perf_counter() - t0
+    base = {"value": m / dt, "unit": "trajectories/s", "cores": 1, "kind": "oracle",
+            "sample": f"trajectories 0..{m - 1} (seed 0), exact-propagator oracle (numpy/scipy, one thread), {dt:.1f} s"}
+    ctx = qtm.create_system(system, qtm.Opts(precision=0, form=qtm.FORM_BATCHED, integrator=qtm.INT_EXPO,
+                                             record_jumps=32, keep_traj=1))
+    ctx.run(m, 0)
+    X = ctx.traj_expect()
+    same, jtd = 0, 0.0
+    for i in range(m):
+        t, c, cnt = ctx.jumps(i)
+        if cnt == r["jump_counts"][i]:
+            same += 1
+            k = min(cnt, 32)
+            if k and np.array_equal(c[:k], r["jump_channels"][i, :k]):
+                jtd = max(jtd, float(np.max(np.abs(t[:k] - r["jump_times"][i, :k]))))
+    ctx.destroy()
+    return base, {"ntraj": m, "seed": 0, "identical_jump_counts": same / m, "max_jump_time_diff": jtd,
+                  "max_output_diff": float(np.max(np.abs(X - r["X"])))}
+
+
 def other_workload(a, qtm, w, torch):
     """One secondary configuration as its own JSON line (--workload NAME)."""
     print(json.dumps(run_secondary(a.workload, qtm, w, torch, a.steps, a.warmup, cpu=not a.no_cpu)), flush=True)
@@ -439,7 +486,7 @@ def main():
     ap.add_argument("--counters", action="store_true",
                     help="short run for rocprofv3 counter passes: two launches of the headline kernel "
                          "(FP32 products, batched, 10,000 trajectories) and a 256 MiB device copy for calibration")
-    ap.add_argument("--workload", default="jcm", choices=["jcm", "two_level", "tfim", "hetero", "trilinear"],
+    ap.add_argument("--workload", default="jcm", choices=["jcm", "two_level", "tfim", "hetero", "trilinear", "stiff"],
                     help="jcm (default, the headline) or a secondary configuration alone")
     ap.add_argument("--no-secondary", action="store_true",
                     help="leave out the secondary configurations nested in the headline line")
@@ -557,7 +604,7 @@ def main():
         # trilinear Hamiltonian), each with its plain form, roofline, CPU baseline and
         # oracle check, nested in the one line
         line["secondary"] = {}
-        for name in ("two_level", "tfim", "hetero", "trilinear"):
+        for name in ("two_level", "tfim", "hetero", "trilinear", "stiff"):
             t0 = time.perf_counter()
             line["secondary"][name] = run_secondary(name, qtm, w, torch, max(2, min(a.steps, 3)), 1, cpu=not a.no_cpu)
             print(f"[bench] secondary {name} done in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
