@@ -321,7 +321,7 @@ def secondary_spec(name, qtm, w):
                           "against the exact propagator (FP64, batched)")
     if name == "hetero":
         s = w.hetero_batch()
-        return dict(systems=s, n=500, batch=True, kernel="traj_team_batch_kernel (three tile classes)", bound="mfma",
+        return dict(systems=s, n=500, batch=True, tune_batch=True, kernel="traj_team_batch_kernel (three tile classes)", bound="mfma",
                     peak=PEAK["fp32"], fps=[6 * 8.0 * x.dim ** 2 + 128.0 * x.dim for x in s], check_n=500,
                     label="hetero_batch 64 systems d~U{8..256}, n_c~U{1..4}, t in [0,20] (101 points), "
                           "500 trajectories each")
@@ -338,6 +338,12 @@ def run_secondary(name, qtm, w, torch, steps, warmup, cpu=True):
     out = {}
     forms = sp.get("forms", (("plain", dict(precision=qtm.PREC_FP64)),
                              ("best", dict(precision=qtm.PREC_FP32, form=qtm.FORM_BATCHED))))
+    tuned = None
+    if sp.get("tune_batch"):
+        # team shape of every tile class, timed by the autotuner on the class's own systems
+        from paper_1810_03047_amd import autotune
+        tuned = autotune.pick_batch_waves(systems, qtm.Opts(precision=qtm.PREC_FP32, form=qtm.FORM_BATCHED), n)
+        forms = (forms[0], ("best", dict(forms[1][1], class_waves=tuned["class_waves"])))
     for form_name, kw in forms:
         o = qtm.Opts(**kw)
         ctx = make(o)
@@ -378,6 +384,9 @@ def run_secondary(name, qtm, w, torch, steps, warmup, cpu=True):
         "config": {"workload": sp["label"], "ntraj": total, "form": "batched+mixed", "parallelism": "trajectories (1 GPU)"},
         "plain": out["plain"], "speedup_vs_plain": b["value"] / out["plain"]["value"],
     }
+    if tuned is not None:
+        line["tuned_class_waves"] = {"class_waves": list(tuned["class_waves"]),
+                                     "kernel_ms": {str(k): v for k, v in tuned["kernel_ms"].items()}}
     if name == "stiff":
         line["dtype"] = "f64"
         line["config"]["form"] = "exact propagator (batched)"
@@ -485,9 +494,12 @@ def main():
     ap.add_argument("--tune-cache", default=None, help="JSON file for the autotuner's choices")
     ap.add_argument("--counters", action="store_true",
                     help="short run for rocprofv3 counter passes: two launches of the headline kernel "
-                         "(FP32 products, batched, 10,000 trajectories) and a 256 MiB device copy for calibration")
+                         "(FP32 products, batched, 10,000 trajectories; or of --workload's batched form) "
+                         "and a 256 MiB device copy for calibration")
     ap.add_argument("--workload", default="jcm", choices=["jcm", "two_level", "tfim", "hetero", "trilinear", "stiff"],
                     help="jcm (default, the headline) or a secondary configuration alone")
+    ap.add_argument("--class-waves", default="",
+                    help="with --counters --workload hetero: waves per team of the three tile classes, e.g. 4,8,8")
     ap.add_argument("--no-secondary", action="store_true",
                     help="leave out the secondary configurations nested in the headline line")
     a = ap.parse_args()
@@ -504,9 +516,23 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     if a.counters:
-        ctx = qtm.create_system(w.jaynes_cummings(), qtm.Opts(precision=qtm.PREC_FP32, form=qtm.FORM_BATCHED, team_waves=1))
-        for i in range(2):
-            ctx.run(NTRAJ, i)
+        if a.workload == "hetero":
+            # the heterogeneous batch's tile-class launches with the shapes the autotuner picks
+            systems = w.hetero_batch()
+            cw = tuple(int(x) for x in a.class_waves.split(",")) if a.class_waves else (0, 0, 0)
+            ctx = qtm.create_batch(systems, qtm.Opts(precision=qtm.PREC_FP32, form=qtm.FORM_BATCHED, class_waves=cw))
+            for i in range(2):
+                ctx.run(500, i)
+        elif a.workload != "jcm":
+            sp = secondary_spec(a.workload, qtm, w)
+            kw = dict(sp["forms"][1][1]) if "forms" in sp else dict(precision=qtm.PREC_FP32, form=qtm.FORM_BATCHED)
+            ctx = qtm.create_system(sp["systems"][0], qtm.Opts(**kw))
+            for i in range(2):
+                ctx.run(sp["n"], i)
+        else:
+            ctx = qtm.create_system(w.jaynes_cummings(), qtm.Opts(precision=qtm.PREC_FP32, form=qtm.FORM_BATCHED, team_waves=1))
+            for i in range(2):
+                ctx.run(NTRAJ, i)
         x = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
         x.fill_(1.0)
         y = torch.empty_like(x)

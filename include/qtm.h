@@ -92,7 +92,11 @@ typedef struct {
                                  one of qtm_tile_candidates() (0: default shape) */
     int32_t integrator;       /* QTM_INT_DOPRI5 (default) or QTM_INT_EXPO */
     int32_t expo_substeps;    /* QTM_INT_EXPO: propagator steps per output interval (0: 1) */
-    int32_t reserved[4];
+    int32_t class_waves[3];   /* batches of dense systems, batched form: waves per 16-trajectory team
+                                 of the tile classes d <= 64, 128, 256, one of
+                                 qtm_batch_tile_candidates(class) (0: the class's default shape;
+                                 -1: the class runs on the sliced-ELL SpMM kernel instead) */
+    int32_t reserved[1];
 } qtm_opts;
 
 /* Integrators.  QTM_INT_DOPRI5: adaptive Dormand-Prince 5(4) with dense output (the
@@ -189,8 +193,11 @@ int qtm_create_td(qtm_ctx** out, const qtm_op* H0, const qtm_op* H_td, const qtm
 
 /* Creates a context holding n_sys systems of mixed dimension (each dense,
  * d <= 256, n_e <= 16) that qtm_run integrates in one persistent launch per
- * tile class.  System s uses Philox key (seed, s).  Errors as qtm_create; the
- * message names the offending system index. */
+ * tile class (batched form).  Inside a class the systems are handed to the
+ * persistent blocks in decreasing order of an estimated cost d^2 x ||M||_inf x
+ * (t_end - t0) (work per step times the steps the norm of M asks for), so that the
+ * largest start first.  System s uses Philox key (seed, s).  Errors as qtm_create;
+ * the message names the offending system index. */
 int qtm_create_batch(qtm_ctx** out, int32_t n_sys, const qtm_system* sys, const qtm_opts* o);
 
 /* Runs trajectories 0..ntraj-1 (of every system of a batch) on the context's
@@ -320,6 +327,11 @@ int qtm_proposal_grad(qtm_ctx* ctx, const float* feat, const float* tgt, int64_t
  * for dimension d, written to waves[0..return-1] (at most cap); the first one
  * is the default.  Used by autotuners; returns 0 when d > 64.  Not a status. */
 int qtm_tile_candidates(int32_t d, int32_t* waves, int32_t cap);
+
+/* Team sizes (wavefronts per 16-trajectory team) the batched tile-class launch offers for
+ * class cls (0, 1, 2: dense systems with d <= 64, 128, 256), written to waves[0..return-1]
+ * (at most cap); the first is the default.  For autotuners; not a status. */
+int qtm_batch_tile_candidates(int32_t cls, int32_t* waves, int32_t cap);
 
 /* ----------------------------------------------------------- misc */
 /* Message of the last failing call in this thread ("" if none).  Not an int. */

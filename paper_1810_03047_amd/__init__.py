@@ -51,7 +51,7 @@ class _Opts(C.Structure):
                 ("max_steps", C.c_int64), ("device", C.c_int32), ("record_jumps", C.c_int32),
                 ("stream", C.c_void_p), ("keep_traj", C.c_int32), ("seg_cap", C.c_int32),
                 ("tile_cols", C.c_int32), ("team_waves", C.c_int32), ("integrator", C.c_int32),
-                ("expo_substeps", C.c_int32), ("reserved", C.c_int32 * 4)]
+                ("expo_substeps", C.c_int32), ("class_waves", C.c_int32 * 3), ("reserved", C.c_int32 * 1)]
 
 
 class _Stats(C.Structure):
@@ -99,6 +99,7 @@ _SIGS = {
     "qtm_train_proposal": (C.c_int, [C.c_void_p, _fp, _fp, C.c_int64, C.c_int32, C.c_int32, C.c_float, C.c_uint64, _fp]),
     "qtm_proposal_grad": (C.c_int, [C.c_void_p, _fp, _fp, C.c_int64, _fp, _fp]),
     "qtm_tile_candidates": (C.c_int, [C.c_int32, _ip, C.c_int32]),
+    "qtm_batch_tile_candidates": (C.c_int, [C.c_int32, _ip, C.c_int32]),
     "qtm_last_error": (C.c_char_p, []),
     "qtm_destroy": (None, [C.c_void_p]),
 }
@@ -109,6 +110,19 @@ def tile_candidates(d: int):
     w = np.zeros(8, dtype=np.int32)
     n = load().qtm_tile_candidates(int(d), _ptr(w, _ip), 8)
     return [int(x) for x in w[:n]]
+
+
+def batch_tile_candidates(cls: int):
+    """Team sizes the batched tile-class launch offers for class cls (d <= 64, 128, 256)."""
+    w = np.zeros(8, dtype=np.int32)
+    n = load().qtm_batch_tile_candidates(int(cls), _ptr(w, _ip), 8)
+    return [int(x) for x in w[:n]]
+
+
+def tile_class(d: int) -> int:
+    """Tile class of a dense system of dimension d in a batch (-1 above 256)."""
+    rt = 2 * ((d + 7) // 8 * 8) // 16
+    return 0 if rt <= 8 else 1 if rt <= 16 else 2 if rt <= 32 else -1
 
 
 def exported_names():
@@ -183,6 +197,7 @@ class Opts:
     team_waves: int = 0
     integrator: int = INT_DOPRI5
     expo_substeps: int = 0
+    class_waves: tuple = (0, 0, 0)     # batched tile classes d <= 64, 128, 256: waves per team (0: default)
     stream: Optional[int] = None      # raw hipStream_t; None: torch's current stream when available
 
     def _c(self) -> _Opts:
@@ -193,6 +208,8 @@ class Opts:
         o.keep_traj, o.seg_cap, o.tile_cols = self.keep_traj, self.seg_cap, self.tile_cols
         o.team_waves = self.team_waves
         o.integrator, o.expo_substeps = self.integrator, self.expo_substeps
+        for k in range(3):
+            o.class_waves[k] = int(self.class_waves[k])
         st = self.stream
         if st is None:
             try:

@@ -217,6 +217,7 @@ struct DevBuf {
 
 struct SysHost {
     int d = 0, n_c = 0, n_e = 0, n_t = 0, n_f = 0;
+    double cost = 0.0;         // estimated work of one trajectory: d^2 ||M||_inf (t_end - t0)
     // exact-propagator integrator: fragments of exp(h 2^-j M), j = 0..expo_J (device)
     bool expo = false;
     const double* expo_P = nullptr;
@@ -247,6 +248,8 @@ struct qtm_ctx {
     long long* d_fail = nullptr;
     unsigned long long* d_counters = nullptr;
     unsigned int* d_cursor = nullptr;
+    int* d_cls_off = nullptr;                // [3][9] offsets of the per-XCD system lists of each tile class
+    unsigned int* d_cls_cur = nullptr;       // [3][8] cursors of those lists
     float* d_mlp = nullptr;            // BF16-rounded weights for inference
     unsigned short* d_mlpf = nullptr;  // the same weights as BF16 matrix-core fragments
     std::vector<float> mlp_master;     // FP32 master weights
@@ -272,6 +275,7 @@ struct qtm_ctx {
     qtm::DevSystem* d_sys_cls = nullptr;
     std::vector<int> cls_sys;                // system index of each entry of d_sys_cls
     int cls_off[3] = {0, 0, 0}, cls_n[3] = {0, 0, 0}, cls_maxd[3] = {0, 0, 0}, cls_maxne[3] = {0, 0, 0};
+    int cls_xoff[3][9] = {};                 // per-XCD list offsets inside each class (host copy)
     int wall_khz = 100000;                   // rate of the device wall clock
 };
 
@@ -412,6 +416,15 @@ int setup_system(SysHost& S, const qtm_system& in, int idx, const qtm_opts& o, b
     D.t0 = in.tlist[0]; D.tend = in.tlist[in.n_t - 1];
     D.key1 = (unsigned long long)idx;
     HCsr M = build_M(H, in.c_ops, in.n_c);
+    {
+        double mn = 0.0;
+        for (int i = 0; i < d; ++i) {
+            double rs = 0.0;
+            for (int p = M.rp[i]; p < M.rp[i + 1]; ++p) rs += std::abs(M.v[p]);
+            mn = std::max(mn, rs);
+        }
+        S.cost = (double)d * d * std::max(mn, 1e-3) * (in.tlist[in.n_t - 1] - in.tlist[0]);
+    }
     if (!S.sparse) {
         int dp = (d + 7) / 8 * 8;
         D.dp = dp;
@@ -783,6 +796,14 @@ void qtm_opts_default(qtm_opts* o) {
 
 const char* qtm_last_error(void) { return g_err.c_str(); }
 
+int qtm_batch_tile_candidates(int32_t cls, int32_t* waves, int32_t cap) {
+    if (!waves || cap < 1) return 0;
+    int tmp[8];
+    int n = std::min(qtm::team_batch_candidates(cls, tmp, 8), (int)cap);
+    for (int i = 0; i < n; ++i) waves[i] = tmp[i];
+    return n;
+}
+
 int qtm_tile_candidates(int32_t d, int32_t* waves, int32_t cap) {
     if (!waves || cap < 1) return 0;
     int tmp[8];
@@ -804,6 +825,14 @@ static int create_common(qtm_ctx** out, int32_t n_sys, const qtm_system* sys, co
     if (opt.max_steps < 1) return fail(QTM_E_INVAL, "max_steps must be >= 1");
     if (opt.record_jumps < 0 || opt.seg_cap < 0) return fail(QTM_E_INVAL, "negative capacity");
     if (opt.team_waves < 0 || opt.tile_cols < 0) return fail(QTM_E_INVAL, "negative tile option");
+    for (int k = 0; k < 3; ++k) {
+        if (opt.class_waves[k] == 0 || opt.class_waves[k] == -1) continue;
+        int w[8];
+        const int n = qtm::team_batch_candidates(k, w, 8);
+        bool ok = false;
+        for (int i = 0; i < n; ++i) ok |= w[i] == opt.class_waves[k];
+        if (!ok) return fail(QTM_E_INVAL, "class_waves[%d] = %d is not offered for that tile class", k, opt.class_waves[k]);
+    }
     if (opt.integrator != QTM_INT_DOPRI5 && opt.integrator != QTM_INT_EXPO) return fail(QTM_E_INVAL, "unknown integrator %d", opt.integrator);
     if (opt.integrator == QTM_INT_EXPO) {
         if (opt.precision != QTM_PREC_FP64) return fail(QTM_E_INVAL, "the exact-propagator integrator uses FP64 products");
@@ -851,10 +880,33 @@ static int create_common(qtm_ctx** out, int32_t n_sys, const qtm_system* sys, co
                         c->cls_maxne[k] = std::max(c->cls_maxne[k], c->sys[s].n_e);
                     }
                 c->cls_n[k] = (int)c->cls_sys.size() - c->cls_off[k];
+                // eight lists, one per XCD, balanced by estimated cost (largest first to the
+                // list with the least cost so far); each list most expensive first
+                std::vector<int> cl(c->cls_sys.begin() + c->cls_off[k], c->cls_sys.end());
+                std::stable_sort(cl.begin(), cl.end(), [&](int x, int y) { return c->sys[x].cost > c->sys[y].cost; });
+                std::vector<std::vector<int>> bins(8);
+                double load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+                for (int s2 : cl) {
+                    int b = (int)(std::min_element(load, load + 8) - load);
+                    bins[b].push_back(s2);
+                    load[b] += c->sys[s2].cost;
+                }
+                c->cls_sys.resize(c->cls_off[k]);
+                c->cls_xoff[k][0] = 0;
+                for (int b = 0; b < 8; ++b) {
+                    c->cls_sys.insert(c->cls_sys.end(), bins[b].begin(), bins[b].end());
+                    c->cls_xoff[k][b + 1] = c->cls_xoff[k][b] + (int)bins[b].size();
+                }
             }
-            if (hipMalloc(&c->d_sys_cls, sizeof(qtm::DevSystem) * n_sys) != hipSuccess) {
+            if (hipMalloc(&c->d_sys_cls, sizeof(qtm::DevSystem) * n_sys) != hipSuccess ||
+                hipMalloc(&c->d_cls_off, sizeof(int) * 27) != hipSuccess ||
+                hipMalloc(&c->d_cls_cur, sizeof(unsigned int) * 24) != hipSuccess) {
                 qtm_destroy(c);
                 return fail(QTM_E_NOMEM, "device allocation failed");
+            }
+            if (hipMemcpy(c->d_cls_off, c->cls_xoff, sizeof(int) * 27, hipMemcpyHostToDevice) != hipSuccess) {
+                qtm_destroy(c);
+                return fail(QTM_E_DEVICE, "upload of the tile-class lists failed");
             }
         }
     }
@@ -919,6 +971,7 @@ static int enqueue_run(qtm_ctx* c, const qtm::RunArgs& a, long long count, hipSt
     if ((rc = fill(c->d_fail, sizeof(long long), (unsigned long long)LLONG_MAX))) return rc;
     if ((rc = fill(c->d_counters, 4 * sizeof(unsigned long long), 0))) return rc;
     if ((rc = fill(c->d_cursor, 4 * sizeof(unsigned long long), 0))) return rc;
+    if (c->d_cls_cur && (rc = fill(c->d_cls_cur, 24 * sizeof(unsigned int), 0))) return rc;
 
     if (qtm::launch_stamp(c->d_stamp, st)) return fail(QTM_E_DEVICE, "timestamp kernel launch failed");
     const bool one_launch = c->batch && c->sys.size() > 1 && (c->o.form & QTM_FORM_BATCHED);
@@ -946,9 +999,23 @@ static int enqueue_run(qtm_ctx* c, const qtm::RunArgs& a, long long count, hipSt
             qtm::RunArgs ak = a;
             ak.sys = c->d_sys_cls + c->cls_off[k];
             ak.n_sys = c->cls_n[k];
-            ak.sys_cursor = (unsigned int*)((unsigned long long*)c->d_cursor + 1 + k);
+            ak.sys_cursor = c->d_cls_cur + 8 * k;
+            ak.xcd_off = c->d_cls_off + 9 * k;
             qtm::LaunchInfo lx{};
-            int lr = qtm::launch_team_batch(ak, c->cls_maxd[k], c->cls_maxne[k], c->o.precision, c->side[k], &lx);
+            int lr;
+            if (c->o.class_waves[k] < 0) {
+                // the class on the SpMM kernel (every system of a batch has its sliced ELL)
+                long long max_ell = 0;
+                for (int q = 0; q < c->cls_n[k]; ++q)
+                    max_ell = std::max(max_ell, c->sys[c->cls_sys[c->cls_off[k] + q]].dev.ell_n);
+                ak.xcd_off = nullptr;
+                const int cols = c->o.tile_cols > 0 ? c->o.tile_cols : (c->o.precision == QTM_PREC_FP32 ? 4 : 2);
+                lr = qtm::launch_sparse(ak, c->sys[c->cls_sys[c->cls_off[k]]].dev, c->cls_maxd[k], max_ell, c->o.precision,
+                                        cols, c->side[k], &lx);
+            } else {
+                lr = qtm::launch_team_batch(ak, c->cls_maxd[k], c->cls_maxne[k], c->o.precision, c->o.class_waves[k],
+                                            c->side[k], &lx);
+            }
             if (lr) return fail(QTM_E_DEVICE, "tile-class launch %d failed (%d): %s", k, lr, hipGetErrorString(hipGetLastError()));
             if (first) { *li = lx; first = false; }
         }
@@ -1470,6 +1537,8 @@ void qtm_destroy(qtm_ctx* c) {
     if (c->d_fail) (void)hipFree(c->d_fail);
     if (c->d_counters) (void)hipFree(c->d_counters);
     if (c->d_cursor) (void)hipFree(c->d_cursor);
+    if (c->d_cls_off) (void)hipFree(c->d_cls_off);
+    if (c->d_cls_cur) (void)hipFree(c->d_cls_cur);
     if (c->d_stamp) (void)hipFree(c->d_stamp);
     if (c->d_sys_cls) (void)hipFree(c->d_sys_cls);
     if (c->d_mlp) (void)hipFree(c->d_mlp);

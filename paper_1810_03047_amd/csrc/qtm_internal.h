@@ -80,7 +80,10 @@ struct DevSystem {
 struct RunArgs {
     const DevSystem* sys;      // device array of systems handled by this launch
     int n_sys;
-    unsigned int* sys_cursor;  // first system that may still have trajectories
+    unsigned int* sys_cursor;  // first system that may still have trajectories (tile classes with
+                               // xcd_off: one cursor per XCD list, absolute system indices)
+    const int* xcd_off;        // tile classes: [9] offsets of the eight per-XCD system lists in sys
+                               // (nullptr: one list)
     double rtol, atol;
     long long max_steps;
     int jcap, seg_cap;
@@ -123,11 +126,13 @@ int mlp_partial_rows(int n);
 int wave_supported(int d);
 int launch_wave(const RunArgs& a, const DevSystem& s0, int prec, int waves_per_team, hipStream_t st, LaunchInfo* info);
 int team_candidates(int d, int* waves, int cap);
-// a batch's dense systems in one persistent launch per tile class (teams of 4 waves with
-// 2, 4 or 8 row tiles per wave for d <= 64, 128, 256), operator A-fragments read from L2;
-// a.sys holds the class's systems; returns -1 when max_d > 256
-int launch_team_batch(const RunArgs& a, int max_d, int max_ne, int prec, hipStream_t st, LaunchInfo* info);
+// a batch's dense systems in one persistent launch per tile class (d <= 64, 128, 256),
+// operator A-fragments read from L2; a.sys holds the class's systems in the order blocks
+// take them; returns -1 when max_d > 256
+// waves: waves per team, one of team_batch_candidates(class) (0: the class's default shape)
+int launch_team_batch(const RunArgs& a, int max_d, int max_ne, int prec, int waves, hipStream_t st, LaunchInfo* info);
 int team_batch_class(int d);      // 0, 1, 2 for d <= 64, 128, 256; -1 above
+int team_batch_candidates(int cls, int* waves, int cap);
 // exact-propagator kernel (qtm_expo.hip), d <= 40, FP64: Pg = fragments of exp(h 2^-j M),
 // j = 0..J; m steps per output interval, NS steps from t0 to t_end
 int launch_expo(const RunArgs& a, const DevSystem& s0, const double* Pg, int J, int m, double h, long long NS,

@@ -78,7 +78,7 @@ struct Team {
     double2* St;             // alias of Wb: complex staging [dp][16]
     double* Xb;              // LDS: team reduction exchange [NWT][16][kXV]
     unsigned long long* Ib;  // LDS: trajectory hand-out [16]
-    int* Fb;                 // LDS: team flags [4]
+    int* Fb;                 // LDS: team flags, one per wave
     const double2* Od;       // LDS copy of the diagonal observables [n_e][d] (when od_lds;
                              // od_lds == 2: every one real)
     const float* Ft;         // LDS: FP32 feature table [d][16] (rows 12, 13: C_n^dag C_n when diagonal)
@@ -1121,7 +1121,7 @@ static __host__ __device__ TeamLds team_lds(int dp, int d, int n_e, int prec, in
     L.x = (size_t)2 * dp * 16 * sizeof(double);                             // offsets inside a team
     L.ib = L.x + (size_t)nwt * 16 * kXV * sizeof(double);
     L.fb = L.ib + 16 * sizeof(unsigned long long);
-    L.team = (L.fb + 16 + 15) & ~(size_t)15;                                // bytes per team
+    L.team = (L.fb + 4 * (size_t)(nwt > 4 ? nwt : 4) + 15) & ~(size_t)15;  // bytes per team (one flag per wave)
     L.od = L.w + (size_t)tpb * L.team;
     L.ft = L.od + (od_lds ? (size_t)n_e * d * sizeof(double2) : 0);
     L.total = L.ft + (size_t)16 * d * sizeof(float);                      // FP32 feature table [d][16]
@@ -1196,7 +1196,7 @@ static __host__ __device__ TeamLds team_lds_batch(int dpmax, int dmax, int nemax
     L.x = (size_t)2 * dpmax * 16 * sizeof(double);
     L.ib = L.x + (size_t)nwt * 16 * kXV * sizeof(double);
     L.fb = L.ib + 16 * sizeof(unsigned long long);
-    L.team = (L.fb + 16 + 15) & ~(size_t)15;
+    L.team = (L.fb + 4 * (size_t)(nwt > 4 ? nwt : 4) + 15) & ~(size_t)15;  // one flag per wave
     L.od = L.team;
     L.ft = L.od + (size_t)nemax * dmax * sizeof(double2);
     L.total = L.ft + (size_t)16 * dmax * sizeof(float);
@@ -1215,20 +1215,30 @@ __global__ void __launch_bounds__(64 * NWT) traj_team_batch_kernel(RunArgs a, in
     const TeamLds L = team_lds_batch(dpmax, dmax, nemax, NWT);
     char* base = (char*)smem;
     unsigned long long passes = 0, pmax = 0;
-    int si = 0;
+    // XCD-aware hand-out: with a.xcd_off the class's systems are split into eight lists,
+    // one per XCD (blocks are dispatched to the XCDs round-robin), so that the blocks of
+    // an XCD share the operators held in that XCD's L2; a block that has emptied its own
+    // list takes work from the others in turn
+    const int nseg = a.xcd_off ? 8 : 1;
+    const int home = a.xcd_off ? (int)(blockIdx.x % 8) : 0;
+    for (int g = 0; g < nseg; ++g) {
+    const int seg = (home + g) % nseg;
+    const int lo = a.xcd_off ? a.xcd_off[seg] : 0, hi = a.xcd_off ? a.xcd_off[seg + 1] : a.n_sys;
+    unsigned int* cursor = a.sys_cursor + seg;
+    int si = lo;
     for (;;) {
         if (threadIdx.x == 0) {
-            int s2 = max(si, (int)__atomic_load_n(a.sys_cursor, __ATOMIC_RELAXED));
-            while (s2 < a.n_sys &&
+            int s2 = max(si, (int)__atomic_load_n(cursor, __ATOMIC_RELAXED));
+            while (s2 < hi &&
                    __atomic_load_n(a.sys[s2].queue, __ATOMIC_RELAXED) >= (unsigned long long)a.sys[s2].count) {
-                atomicMax(a.sys_cursor, (unsigned int)(s2 + 1));
+                atomicMax(cursor, (unsigned int)(s2 + 1));
                 ++s2;
             }
             cur = s2;
         }
         __syncthreads();
         si = cur;
-        if (si >= a.n_sys) break;
+        if (si >= hi) break;
         const DevSystem& S = a.sys[si];
         int od_lds = S.any_csr_e ? 0 : 2;
         for (int o = 0; o < S.n_e && od_lds; ++o) if (S.e_nv[o] != 1) od_lds = 1;
@@ -1267,6 +1277,7 @@ __global__ void __launch_bounds__(64 * NWT) traj_team_batch_kernel(RunArgs a, in
         pmax = W.passes > pmax ? W.passes : pmax;
         __syncthreads();                 // the block leaves the system together
         ++si;
+    }
     }
     if (threadIdx.x == 0) {
         atomicAdd(&a.counters[0], passes);

@@ -352,3 +352,49 @@ def test_trained_proposal_gains_over_starting_step_rule():
     assert losses[-1] < losses[0]
     assert res["learned"][0] < res["rule"][0]
     assert res["learned"][2] < res["rule"][2]
+
+
+@pytest.mark.parametrize("class_waves", [(0, 0, 0), (8, 8, 4), (4, 4, 16)])
+def test_batch_tile_class_shapes_fp64_exact(class_waves):
+    """Every team shape offered for the three tile classes of a batch (d <= 64, 128, 256)
+    gives the oracle's FP64 trajectories; the systems run in cost order."""
+    rng = np.random.Generator(np.random.Philox(key=12))
+    dims = [16, 56, 72, 120, 136, 250]
+    systems = [w.random_system(rng, d, 1 + i % 3, t_end=3.0, n_t=16, c_norm=0.3) for i, d in enumerate(dims)]
+    n = 32
+    print(f"[gpu] batch tile classes dims={dims} class_waves={class_waves} ntraj={n}", flush=True)
+    ctx = qtm.create_batch(systems, qtm.Opts(form=qtm.FORM_BATCHED, record_jumps=32, keep_traj=1,
+                                             class_waves=class_waves))
+    ctx.run(n, 13)
+    for sidx, s in enumerate(systems):
+        r = oracle.run(s, n, seed=13, sys_id=sidx, jcap=32)
+        jn = np.array([ctx.jumps(i, system=sidx)[2] for i in range(n)])
+        assert np.array_equal(jn, r["jump_counts"]), (sidx, np.nonzero(jn != r["jump_counts"]))
+        X = ctx.traj_expect(sidx)
+        assert np.max(np.abs(X - r["X"])) <= 1e-8, sidx
+
+
+def test_batch_tile_class_shape_rejected():
+    rng = np.random.Generator(np.random.Philox(key=12))
+    systems = [w.random_system(rng, d, 1, t_end=1.0, n_t=3) for d in (16, 24)]
+    with pytest.raises(qtm.QtmError):
+        qtm.create_batch(systems, qtm.Opts(form=qtm.FORM_BATCHED, class_waves=(5, 0, 0)))
+    assert qtm.batch_tile_candidates(2) == [8, 4, 16]
+
+
+def test_batch_tile_class_on_spmm_kernel_fp64_exact():
+    """class_waves = -1 runs a tile class on the sliced-ELL SpMM kernel inside the batched
+    launch: the oracle's FP64 trajectories as well."""
+    rng = np.random.Generator(np.random.Philox(key=14))
+    dims = [20, 48, 90, 110, 180, 230]
+    systems = [w.random_system(rng, d, 1 + i % 3, t_end=3.0, n_t=16, c_norm=0.3) for i, d in enumerate(dims)]
+    n = 32
+    print(f"[gpu] batch tile classes on SpMM dims={dims} ntraj={n}", flush=True)
+    ctx = qtm.create_batch(systems, qtm.Opts(form=qtm.FORM_BATCHED, record_jumps=32, keep_traj=1,
+                                             class_waves=(-1, -1, -1)))
+    ctx.run(n, 15)
+    for sidx, s in enumerate(systems):
+        r = oracle.run(s, n, seed=15, sys_id=sidx, jcap=32)
+        jn = np.array([ctx.jumps(i, system=sidx)[2] for i in range(n)])
+        assert np.array_equal(jn, r["jump_counts"]), (sidx, np.nonzero(jn != r["jump_counts"]))
+        assert np.max(np.abs(ctx.traj_expect(sidx) - r["X"])) <= 1e-8, sidx
