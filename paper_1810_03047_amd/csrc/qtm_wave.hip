@@ -916,8 +916,18 @@ struct Team {
             }
         }
         const bool anyj = team_any(action == ACT_JUMP);
-        if (anyj) jump_time();
-        if (team_any(action == ACT_ACCEPT || action == ACT_JUMP)) outputs_loop(1);
+        if (NWT == 1 && od_lds == 2 && S.n_e <= 2) {
+            // real diagonal observables: one Gram pass per step serves the jump time and
+            // every output time of every lane
+            const bool need = action == ACT_JUMP || (action == ACT_ACCEPT && kk < S.n_t && tnext <= tb);
+            if (team_any(need)) {
+                if (S.n_e == 1) gram_outputs<1>(need);
+                else gram_outputs<2>(need);
+            }
+        } else {
+            if (anyj) jump_time();
+            if (team_any(action == ACT_ACCEPT || action == ACT_JUMP)) outputs_loop(1);
+        }
         if (anyj) do_jump();
         if (action == ACT_ACCEPT) {
 #pragma unroll
@@ -931,49 +941,104 @@ struct Team {
         }
     }
 
-    // Jump time: first theta in [0,1] with ||u(theta)||^2 = r, from the Gram matrix of
-    // v = {y, D, B, R4, R5}: u = sum_p c_p v_p, c = (1, th, th(1-th), th^2(1-th), th^2(1-th)^2)
-    QTM_DI void jump_time() {
-        const bool on = action == ACT_JUMP;
-        double g[15];
+    // The five coefficient vectors of the dense output of element e, in FP64:
+    // v = {y, D, B, R4, R5} with u(th) = sum_a c_a(th) v_a, c = (1, th, th(1-th), th^2(1-th), th^2(1-th)^2)
+    QTM_DI void dense_vectors(int e, double2 (&v)[5]) const {
+        v[0] = y[e];
+        v[1] = csub(yn[e], y[e]);
+        v[2] = csub(cscale(h, to_d2(k[0][e])), v[1]);
+        v[3] = csub(csub(v[1], cscale(h, to_d2(k[6][e]))), v[2]);
+        v[4] = cscale(h, cfma(dp_d(6), to_d2(k[6][e]), to_d2(ds[e])));
+    }
+
+    // Gram matrices of the dense output, reduced over the team, for the lanes with on set:
+    // G[0][ab] = Re <v_a, v_b> and G[1 + j][ab] = Re <v_a, O_j v_b> for the NO real
+    // diagonal observables O_j (upper triangle a <= b, 15 values each).  Then
+    // <u(th)|O|u(th)> = sum_ab c_a(th) c_b(th) G[.][ab] for every th of the step.
+    template <int NO> QTM_DI void gram_sums(bool on, double (&G)[NO + 1][15]) {
 #pragma unroll
-        for (int n = 0; n < 15; ++n) g[n] = 0.0;
+        for (int o = 0; o <= NO; ++o)
+#pragma unroll
+            for (int n = 0; n < 15; ++n) G[o][n] = 0.0;
         if (on) {
+            const int qb = qbase();
 #pragma unroll
             for (int e = 0; e < NE; ++e) {
-                int q = comp(e);
-                if (q < 0) continue;
+                const int q = qb + cst(e);
+                if (q >= d) continue;
                 double2 v[5];
-                v[0] = y[e];
-                v[1] = csub(yn[e], y[e]);
-                v[2] = csub(cscale(h, to_d2(k[0][e])), v[1]);
-                v[3] = csub(csub(v[1], cscale(h, to_d2(k[6][e]))), v[2]);
-                v[4] = cscale(h, cfma(dp_d(6), to_d2(k[6][e]), to_d2(ds[e])));
+                dense_vectors(e, v);
+                double w[NO];
+#pragma unroll
+                for (int j = 0; j < NO; ++j) w[j] = Od[(size_t)j * d + q].x;
                 int n = 0;
 #pragma unroll
                 for (int a = 0; a < 5; ++a)
 #pragma unroll
                     for (int b = a; b < 5; ++b) {
-                        g[n] += v[a].x * v[b].x + v[a].y * v[b].y;
+                        const double pab = v[a].x * v[b].x + v[a].y * v[b].y;
+                        G[0][n] += pab;
+#pragma unroll
+                        for (int j = 0; j < NO; ++j) G[1 + j][n] = fma(w[j], pab, G[1 + j][n]);
                         ++n;
                     }
             }
         }
-        {
-            // two team reductions of at most kXV values
-            double g0[8], g1[7];
+        // team reductions of kXV values at a time
+        constexpr int NV = (NO + 1) * 15;
 #pragma unroll
-            for (int n = 0; n < 8; ++n) g0[n] = g[n];
+        for (int c0 = 0; c0 < NV; c0 += kXV) {
+            double tmp[kXV];
 #pragma unroll
-            for (int n = 0; n < 7; ++n) g1[n] = g[8 + n];
-            tsum<8>(g0);
-            tsum<7>(g1);
+            for (int i = 0; i < kXV; ++i) tmp[i] = c0 + i < NV ? G[(c0 + i) / 15][(c0 + i) % 15] : 0.0;
+            tsum<kXV>(tmp);
 #pragma unroll
-            for (int n = 0; n < 8; ++n) g[n] = g0[n];
-#pragma unroll
-            for (int n = 0; n < 7; ++n) g[8 + n] = g1[n];
+            for (int i = 0; i < kXV; ++i)
+                if (c0 + i < NV) G[(c0 + i) / 15][(c0 + i) % 15] = tmp[i];
         }
-        if (on) {
+    }
+
+    // sum_ab c_a(th) c_b(th) g[ab] (upper triangle, off-diagonal terms twice)
+    QTM_DI static double gram_at(const double (&g)[15], const double (&c)[5]) {
+        double v = 0.0;
+        int n = 0;
+#pragma unroll
+        for (int a = 0; a < 5; ++a)
+#pragma unroll
+            for (int b = a; b < 5; ++b) {
+                v = fma((a == b ? 1.0 : 2.0) * c[a] * c[b], g[n], v);
+                ++n;
+            }
+        return v;
+    }
+
+    // Outputs inside the step from the Gram matrices: each lane evaluates its own output
+    // times, t < t_k <= t + h (accepted step; t_k = t + h from y_new) or t < t_k < t*
+    // (jump step), as quadratic forms in th; no team reduction per output time
+    template <int NO> QTM_DI void outputs_gram(const double (&G)[NO + 1][15]) {
+        const bool acc = action == ACT_ACCEPT, jmp = action == ACT_JUMP;
+        for (;;) {
+            const double tk = tnext;
+            const bool out = kk < S.n_t && ((acc && tk <= tb) || (jmp && tk < tb));
+            if (!out) break;
+            const double th = (acc && tk == tb) ? 1.0 : (tk - t) / h;
+            const double t1 = 1.0 - th;
+            const double c[5] = {1.0, th, th * t1, th * th * t1, th * th * t1 * t1};
+            const double nn = gram_at(G[0], c);
+            if (lg == 0 && wv == 0) {
+#pragma unroll
+                for (int j = 0; j < NO; ++j)
+                    S.X[((size_t)traj * S.n_e + j) * S.n_t + kk] = make_double2(gram_at(G[1 + j], c) / nn, 0.0);
+            }
+            kk++;
+            tnext = tnext2;
+            tnext2 = kk + 1 < S.n_t ? S.tlist[kk + 1] : 0.0;
+        }
+    }
+
+    // jump time of the lanes with action ACT_JUMP from the reduced Gram matrix of the norm
+    QTM_DI void jump_root(const double (&g)[15]) {
+        if (action == ACT_JUMP) {
             // ||u(theta)||^2 as a degree-8 polynomial: P_k = sum_{a<=b} w_ab G_ab [theta^k] c_a c_b
             double P[9];
 #pragma unroll
@@ -1015,6 +1080,54 @@ struct Team {
             th = 0.5 * (lo + hi);
             tb = t + th * h;
         }
+    }
+
+    // Jump time: first theta in [0,1] with ||u(theta)||^2 = r, from the Gram matrix of
+    // v = {y, D, B, R4, R5}: u = sum_p c_p v_p, c = (1, th, th(1-th), th^2(1-th), th^2(1-th)^2)
+    QTM_DI void jump_time() {
+        const bool on = action == ACT_JUMP;
+        double g[15];
+#pragma unroll
+        for (int n = 0; n < 15; ++n) g[n] = 0.0;
+        if (on) {
+#pragma unroll
+            for (int e = 0; e < NE; ++e) {
+                int q = comp(e);
+                if (q < 0) continue;
+                double2 v[5];
+                dense_vectors(e, v);
+                int n = 0;
+#pragma unroll
+                for (int a = 0; a < 5; ++a)
+#pragma unroll
+                    for (int b = a; b < 5; ++b) {
+                        g[n] += v[a].x * v[b].x + v[a].y * v[b].y;
+                        ++n;
+                    }
+            }
+        }
+        {
+            // two team reductions of at most kXV values
+            double g0[8], g1[7];
+#pragma unroll
+            for (int n = 0; n < 8; ++n) g0[n] = g[n];
+#pragma unroll
+            for (int n = 0; n < 7; ++n) g1[n] = g[8 + n];
+            tsum<8>(g0);
+            tsum<7>(g1);
+#pragma unroll
+            for (int n = 0; n < 8; ++n) g[n] = g0[n];
+#pragma unroll
+            for (int n = 0; n < 7; ++n) g[8 + n] = g1[n];
+        }
+        jump_root(g);
+    }
+
+    template <int NO> QTM_DI void gram_outputs(bool need) {
+        double G[NO + 1][15];
+        gram_sums<NO>(need, G);
+        jump_root(G[0]);
+        outputs_gram<NO>(G);
     }
 
     // ||C_n psi*||^2 for this lane's trajectory (psi* staged); uniform call
