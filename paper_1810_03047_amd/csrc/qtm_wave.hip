@@ -918,7 +918,8 @@ struct Team {
         const bool anyj = team_any(action == ACT_JUMP);
         if (NWT == 1 && od_lds == 2 && S.n_e <= 2) {
             // real diagonal observables: one Gram pass per step serves the jump time and
-            // every output time of every lane
+            // every output time of every lane (the lanes' own Gram matrices: a trajectory's
+            // results do not depend on its wave neighbours)
             const bool need = action == ACT_JUMP || (action == ACT_ACCEPT && kk < S.n_t && tnext <= tb);
             if (team_any(need)) {
                 if (S.n_e == 1) gram_outputs<1>(need);
@@ -998,37 +999,38 @@ struct Team {
         }
     }
 
-    // sum_ab c_a(th) c_b(th) g[ab] (upper triangle, off-diagonal terms twice)
-    QTM_DI static double gram_at(const double (&g)[15], const double (&c)[5]) {
+    // sum_ab c_a(th) c_b(th) g[ab] over the upper triangle, with the weights
+    // wq[ab] = c_a c_b (a == b) or 2 c_a c_b (a < b)
+    QTM_DI static double gram_at(const double (&g)[15], const double (&wq)[15]) {
         double v = 0.0;
-        int n = 0;
 #pragma unroll
-        for (int a = 0; a < 5; ++a)
-#pragma unroll
-            for (int b = a; b < 5; ++b) {
-                v = fma((a == b ? 1.0 : 2.0) * c[a] * c[b], g[n], v);
-                ++n;
-            }
+        for (int n = 0; n < 15; ++n) v = fma(wq[n], g[n], v);
         return v;
     }
 
     // Outputs inside the step from the Gram matrices: each lane evaluates its own output
     // times, t < t_k <= t + h (accepted step; t_k = t + h from y_new) or t < t_k < t*
     // (jump step), as quadratic forms in th; no team reduction per output time
-    template <int NO> QTM_DI void outputs_gram(const double (&G)[NO + 1][15]) {
+    template <int NO> QTM_DI void outputs_gram(bool on, const double (&G)[NO + 1][15]) {
         const bool acc = action == ACT_ACCEPT, jmp = action == ACT_JUMP;
-        for (;;) {
+        while (on) {
             const double tk = tnext;
             const bool out = kk < S.n_t && ((acc && tk <= tb) || (jmp && tk < tb));
             if (!out) break;
             const double th = (acc && tk == tb) ? 1.0 : (tk - t) / h;
             const double t1 = 1.0 - th;
             const double c[5] = {1.0, th, th * t1, th * th * t1, th * th * t1 * t1};
-            const double nn = gram_at(G[0], c);
+            double wq[15];                      // weights of the quadratic form, shared by all values
+            int n = 0;
+#pragma unroll
+            for (int a = 0; a < 5; ++a)
+#pragma unroll
+                for (int b = a; b < 5; ++b) wq[n++] = (a == b ? c[a] : 2.0 * c[a]) * c[b];
+            const double inn = 1.0 / gram_at(G[0], wq);
             if (lg == 0 && wv == 0) {
 #pragma unroll
                 for (int j = 0; j < NO; ++j)
-                    S.X[((size_t)traj * S.n_e + j) * S.n_t + kk] = make_double2(gram_at(G[1 + j], c) / nn, 0.0);
+                    S.X[((size_t)traj * S.n_e + j) * S.n_t + kk] = make_double2(gram_at(G[1 + j], wq) * inn, 0.0);
             }
             kk++;
             tnext = tnext2;
@@ -1127,11 +1129,11 @@ struct Team {
         double G[NO + 1][15];
         gram_sums<NO>(need, G);
         jump_root(G[0]);
-        outputs_gram<NO>(G);
+        outputs_gram<NO>(need, G);
     }
 
-    // ||C_n psi*||^2 for this lane's trajectory (psi* staged); uniform call
-    QTM_DI double chan_prob(int n, bool on) {
+    // this lane's part of ||C_n psi*||^2 (psi* staged), before the team reduction
+    QTM_DI double chan_part(int n, bool on) const {
         double acc = 0.0;
         if (S.c_isdiag) {
             const double* g = S.f_diag + (size_t)(12 + n) * S.d;
@@ -1148,8 +1150,11 @@ struct Team {
                 if (on && q >= 0) acc += cabs2(csr_row(rp, S.c_ci, S.c_val, q));
             }
         }
-        return tsum1(acc);
+        return acc;
     }
+
+    // ||C_n psi*||^2 for this lane's trajectory (psi* staged); uniform call
+    QTM_DI double chan_prob(int n, bool on) { return tsum1(chan_part(n, on)); }
 
     QTM_DI void do_jump() {
         const bool on = action == ACT_JUMP;
@@ -1164,14 +1169,24 @@ struct Team {
             }
             team_sync();
         }
-        // channel: smallest n with sum_{m<=n} p_m >= u * sum p (two uniform passes)
-        double tot = 0.0;
-        for (int n = 0; n < S.n_c; ++n) tot += chan_prob(n, on);
+        // channel: smallest n with sum_{m<=n} p_m >= u * sum p; the probabilities of
+        // kXV channels at a time in one team reduction
+        double tot = 0.0, pn[kMaxC];
+        for (int n0 = 0; n0 < S.n_c; n0 += kXV) {
+            double pc[kXV];
+#pragma unroll
+            for (int i = 0; i < kXV; ++i) pc[i] = n0 + i < S.n_c ? chan_part(n0 + i, on) : 0.0;
+            tsum<kXV>(pc);
+#pragma unroll
+            for (int i = 0; i < kXV; ++i)
+                if (n0 + i < S.n_c) pn[n0 + i] = pc[i];
+        }
+        for (int n = 0; n < S.n_c; ++n) tot += pn[n];
         const double thr = u * tot;
         double cum = 0.0, plast = 0.0, pch = 0.0;
         int lastpos = -1, chosen = -1;
         for (int n = 0; n < S.n_c; ++n) {
-            double pv = chan_prob(n, on);
+            const double pv = pn[n];
             cum += pv;
             if (pv > 0.0) { lastpos = n; plast = pv; }
             if (chosen < 0 && pv > 0.0 && cum >= thr) { chosen = n; pch = pv; }
@@ -1351,6 +1366,9 @@ __global__ void __launch_bounds__(64 * NWT) traj_team_batch_kernel(RunArgs a, in
         }
         __syncthreads();
         si = cur;
+        // every wave has read cur before thread 0 may write it again: on the break path
+        // the next write (the next list's hand-out) follows with no other barrier between
+        __syncthreads();
         if (si >= hi) break;
         const DevSystem& S = a.sys[si];
         int od_lds = S.any_csr_e ? 0 : 2;
