@@ -1,7 +1,9 @@
 // qtm_sparse.hip -- trajectory kernel for sparse H_eff: sliced-ELL SpMM, each thread
 // owns RPT state components (rows) of the block's NBC trajectories, the column block
 // staged in LDS.  Blocks of 256 threads: the register file then holds the state
-// without spilling (a 1024-thread block would cap every lane at 128 registers).
+// without spilling (a 1024-thread block would cap every lane at 128 registers).  Wide
+// blocks of 512 threads with half the rows per thread: two waves per SIMD, which hide
+// each other's LDS latency in the SpMM, for the same trajectories per block.
 #include "qtm_body.h"
 
 namespace qtm {
@@ -13,8 +15,8 @@ static_assert(sizeof(DevSystem) % 8 == 0, "the descriptor is copied to LDS in 8-
 // takes the first system whose trajectory queue is not exhausted, runs it with
 // slot refill until its queue runs dry, then moves on.  a.sys_cursor records the
 // first system that may still have work, so finished systems are skipped.
-template <int RPT, int NBC, int PREC>
-__global__ void __launch_bounds__(kSparseThreads) traj_sparse_kernel(RunArgs a) {
+template <int RPT, int NBC, int PREC, int NT = kSparseThreads>
+__global__ void __launch_bounds__(NT) traj_sparse_kernel(RunArgs a) {
     extern __shared__ __attribute__((aligned(16))) double smem[];   // 16-byte base: double2 staging
     __shared__ int flags[8];
     __shared__ int cur;
@@ -103,11 +105,17 @@ __global__ void __launch_bounds__(kSparseThreads) traj_sparse_kernel(RunArgs a) 
 // instances (rows per thread x trajectories per block, rows x trajectories <= 8) live in
 // qtm_sparse_r*.hip so that they compile in parallel
 template <int R, int C, int P> const void* sparse_fn_inst();
+template <int R, int C, int P> const void* sparse_fn_wide();
 
 int launch_sparse(const RunArgs& a0, const DevSystem& s0, int max_d, long long max_ell, int prec, int cols,
                   hipStream_t st, LaunchInfo* info) {
     RunArgs a = a0;
-    const int threads = max_d >= kSparseThreads ? kSparseThreads : ((max_d + 63) / 64) * 64;
+    // 512 < d <= 1024: wide blocks, two rows per thread and at most two trajectories per
+    // block (Ising chain L = 10, d = 1024: 691 ms against 748 in FP32, 1,202 against
+    // 1,293 in FP64); at d <= 512 the 256-thread blocks stay faster
+    const bool wide = max_d > 2 * kSparseThreads && max_d <= 4 * kSparseThreads;
+    if (wide && cols > 2) cols = 2;
+    const int threads = wide ? 2 * kSparseThreads : max_d >= kSparseThreads ? kSparseThreads : ((max_d + 63) / 64) * 64;
     int rpt = (max_d + threads - 1) / threads;
     if (rpt == 3) rpt = 4;
     if (rpt > 4 && rpt <= 8) rpt = 8;
@@ -126,6 +134,13 @@ int launch_sparse(const RunArgs& a0, const DevSystem& s0, int max_d, long long m
     QTM_SPARSE_CASE(2, 1) QTM_SPARSE_CASE(2, 2) QTM_SPARSE_CASE(2, 4)
     QTM_SPARSE_CASE(4, 1) QTM_SPARSE_CASE(4, 2) QTM_SPARSE_CASE(8, 1)
 #undef QTM_SPARSE_CASE
+    if (wide) {
+        fn = nullptr;
+#define QTM_SPARSE_WIDE(R, C) \
+    if (rpt == R && cols == C) fn = prec == 0 ? sparse_fn_wide<R, C, 0>() : sparse_fn_wide<R, C, 1>();
+        QTM_SPARSE_WIDE(2, 1) QTM_SPARSE_WIDE(2, 2)
+#undef QTM_SPARSE_WIDE
+    }
     if (!fn) return -1;
     // the sliced ELL joins the LDS when it fits there (16-bit columns) and the block
     // count per CU stays what the registers and the staging allow
