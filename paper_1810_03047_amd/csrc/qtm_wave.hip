@@ -82,6 +82,8 @@ struct Team {
     const double2* Od;       // LDS copy of the diagonal observables [n_e][d] (when od_lds;
                              // od_lds == 2: every one real)
     const float* Ft;         // LDS: FP32 feature table [d][16] (rows 12, 13: C_n^dag C_n when diagonal)
+    const int* Cjc = nullptr;      // LDS jump table (one entry per row of each C_n): column, -1 for none
+    const double2* Cjv = nullptr;  // and value, [n_c][d]; nullptr: the CSR arrays in global memory
     int od_lds;
     int lane, lg, c16, wv, RT, d, dp, q0;
 
@@ -1201,7 +1203,16 @@ struct Team {
             for (int e = 0; e < NE; ++e) {
                 int q = comp(e);
                 if (q < 0) { y[e] = make_double2(0.0, 0.0); continue; }
-                if (ch >= 0) y[e] = cscale(1.0 / sqrt(pch), csr_row(S.c_rp + (size_t)ch * (S.d + 1), S.c_ci, S.c_val, q));
+                if (ch >= 0) {
+                    double2 cv;
+                    if (Cjc) {
+                        const int j = ch * S.d + q, c = Cjc[j];
+                        cv = c >= 0 ? cmul(Cjv[j], St[c * 16 + c16]) : make_double2(0.0, 0.0);
+                    } else {
+                        cv = csr_row(S.c_rp + (size_t)ch * (S.d + 1), S.c_ci, S.c_val, q);
+                    }
+                    y[e] = cscale(1.0 / sqrt(pch), cv);
+                }
                 else { y[e] = St[q * 16 + c16]; nrm += cabs2(y[e]); }
             }
         }
@@ -1239,9 +1250,10 @@ struct Team {
 // LDS][per team: operand tile, team exchange, hand-out, flags][diagonal observables][FP32
 // feature table].  Blocks of single-wave teams hold TPB teams that share M and never meet
 // at a barrier after the set-up.
-struct TeamLds { size_t m, team, w, x, ib, fb, od, ft, total; };
+struct TeamLds { size_t m, team, w, x, ib, fb, od, ft, cj, total; };
+// ncj: channels of the LDS jump table (one entry per row: column, value), 0 for none
 static __host__ __device__ TeamLds team_lds(int dp, int d, int n_e, int prec, int nwt, int tpb, int od_lds,
-                                            int ntd = 0) {
+                                            int ntd = 0, int ncj = 0) {
     TeamLds L;
     size_t es = prec == 0 ? 8 : 4;
     L.m = 0;
@@ -1252,19 +1264,24 @@ static __host__ __device__ TeamLds team_lds(int dp, int d, int n_e, int prec, in
     L.team = (L.fb + 4 * (size_t)(nwt > 4 ? nwt : 4) + 15) & ~(size_t)15;  // bytes per team (one flag per wave)
     L.od = L.w + (size_t)tpb * L.team;
     L.ft = L.od + (od_lds ? (size_t)n_e * d * sizeof(double2) : 0);
-    L.total = L.ft + (size_t)16 * d * sizeof(float);                      // FP32 feature table [d][16]
+    L.cj = (L.ft + (size_t)16 * d * sizeof(float) + 15) & ~(size_t)15;   // after the FP32 feature table [d][16]
+    L.total = L.cj + (size_t)ncj * d * (sizeof(double2) + sizeof(int));
     return L;
 }
 
 // td_lds (TD instances): the time-dependent terms' fragments are copied into LDS after M
-// (otherwise read from global memory)
+// (otherwise read from global memory).  cj_lds: every C_n has at most one entry per row,
+// and the (column, value) of each row's entry is tabulated in LDS for the jumps (otherwise
+// the rows are read from the CSR arrays in global memory, a chain of dependent loads).
 template <int T, int NWT, int PREC, int BAND = 0, bool TD = false>
-__global__ void __launch_bounds__(NWT == 1 ? 256 : 64 * NWT) traj_team_kernel(RunArgs a, int od_lds, int tpb, int td_lds) {
+__global__ void __launch_bounds__(NWT == 1 ? 256 : 64 * NWT) traj_team_kernel(RunArgs a, int od_lds, int tpb, int td_lds,
+                                                                              int cj_lds) {
     typedef typename MfmaT<PREC>::in_t in_t;
     extern __shared__ double smem[];
     const DevSystem& S = a.sys[0];
     const int ntd_lds = (TD && td_lds) ? S.n_td : 0;
-    const TeamLds L = team_lds(S.dp, S.d, S.n_e, PREC, NWT, tpb, od_lds, ntd_lds);
+    const int ncj = cj_lds ? S.n_c : 0;
+    const TeamLds L = team_lds(S.dp, S.d, S.n_e, PREC, NWT, tpb, od_lds, ntd_lds, ncj);
     char* base = (char*)smem;
     const in_t* Mg = MfmaT<PREC>::frag(S);
     in_t* Ml = (in_t*)(base + L.m);
@@ -1286,6 +1303,16 @@ __global__ void __launch_bounds__(NWT == 1 ? 256 : 64 * NWT) traj_team_kernel(Ru
         const bool have = row < 12 || (row < 14 && S.c_isdiag && row - 12 < S.n_c);
         Ftl[i] = have ? (float)S.f_diag[(size_t)row * S.d + q] : 0.f;
     }
+    double2* Cjv = (double2*)(base + L.cj);
+    int* Cjc = (int*)(Cjv + (size_t)ncj * S.d);
+    for (int i = threadIdx.x; i < ncj * S.d; i += blockDim.x) {
+        const int n = i / S.d, q = i - n * S.d;
+        const int* rp = S.c_rp + (size_t)n * (S.d + 1);
+        const int p0 = rp[q];
+        const bool has = rp[q + 1] > p0;
+        Cjc[i] = has ? S.c_ci[p0] : -1;
+        Cjv[i] = has ? S.c_val[p0] : make_double2(0.0, 0.0);
+    }
     __syncthreads();
     const int team = (threadIdx.x >> 6) / NWT;
     char* tb = base + L.w + (size_t)team * L.team;
@@ -1300,6 +1327,8 @@ __global__ void __launch_bounds__(NWT == 1 ? 256 : 64 * NWT) traj_team_kernel(Ru
     W.Od = Odl;
     W.od_lds = od_lds;
     W.Ft = Ftl;
+    W.Cjc = ncj ? Cjc : nullptr;
+    W.Cjv = Cjv;
     W.lane = threadIdx.x & 63;
     W.wv = (threadIdx.x >> 6) % NWT;
     W.lg = W.lane >> 4;
@@ -1512,6 +1541,11 @@ int launch_wave(const RunArgs& a, const DevSystem& s0, int prec, int waves_per_t
         if (ltd == 0) { td_lds = 0; ltd = team_block_lds(dp, s0, prec, nwt, od_lds, &tpb); }
         if (ltd == 0 && od_lds) { od_lds = 0; ltd = team_block_lds(dp, s0, prec, nwt, od_lds, &tpb); }
         if (ltd == 0) return -2;
+        int cj_lds = 0;
+        if (s0.c_isdiag && s0.n_c > 0) {
+            const size_t l2 = team_lds(dp, s0.d, s0.n_e, prec, nwt, tpb, od_lds, td_lds ? s0.n_td : 0, s0.n_c).total;
+            if (l2 <= 160 * 1024) { ltd = l2; cj_lds = 1; }
+        }
         const void* fn = team_fn_td(T, nwt, prec);
         if (!fn) return -1;
         if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)ltd) != hipSuccess) return -3;
@@ -1525,7 +1559,7 @@ int launch_wave(const RunArgs& a, const DevSystem& s0, int prec, int waves_per_t
         long long blocks = a.persistent ? (long long)ncu * nb : need;
         if (blocks > need) blocks = need;
         if (blocks < 1) blocks = 1;
-        void* args[] = {(void*)&a, (void*)&od_lds, (void*)&tpb, (void*)&td_lds};
+        void* args[] = {(void*)&a, (void*)&od_lds, (void*)&tpb, (void*)&td_lds, (void*)&cj_lds};
         if (hipLaunchKernel(fn, dim3((unsigned)blocks), dim3(threads), args, ltd, st) != hipSuccess) return -3;
         if (info) {
             info->blocks = (int)blocks; info->threads = threads; info->lds = (int)ltd; info->cols = cols;
@@ -1553,6 +1587,12 @@ int launch_wave(const RunArgs& a, const DevSystem& s0, int prec, int waves_per_t
     if (nwt == 1 && s0.tile_band && T == 4) fn = prec == 0 ? team_fn_band_inst<4, 0>() : team_fn_band_inst<4, 1>();
     if (nwt == 1 && s0.tile_band && T == 5) fn = prec == 0 ? team_fn_band_inst<5, 0>() : team_fn_band_inst<5, 1>();
     if (!fn) return -1;
+    // the jump table joins the LDS when it fits without fewer teams per block
+    int cj_lds = 0;
+    if (s0.c_isdiag && s0.n_c > 0) {
+        const size_t l2 = team_lds(dp, s0.d, s0.n_e, prec, nwt, tpb, od_lds, 0, s0.n_c).total;
+        if (l2 <= 160 * 1024) { lds = l2; cj_lds = 1; }
+    }
     TeamLds L;
     L.total = lds;
     if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.total) != hipSuccess) return -3;
@@ -1567,7 +1607,7 @@ int launch_wave(const RunArgs& a, const DevSystem& s0, int prec, int waves_per_t
     if (blocks > need) blocks = need;
     if (blocks < 1) blocks = 1;
     int td_lds = 0;
-    void* args[] = {(void*)&a, (void*)&od_lds, (void*)&tpb, (void*)&td_lds};
+    void* args[] = {(void*)&a, (void*)&od_lds, (void*)&tpb, (void*)&td_lds, (void*)&cj_lds};
     if (hipLaunchKernel(fn, dim3((unsigned)blocks), dim3(threads), args, L.total, st) != hipSuccess) return -3;
     const bool band = nwt == 1 && s0.tile_band && (T == 4 || T == 5);
     if (info) {
