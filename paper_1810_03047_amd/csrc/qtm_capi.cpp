@@ -277,6 +277,10 @@ struct qtm_ctx {
     int cls_off[3] = {0, 0, 0}, cls_n[3] = {0, 0, 0}, cls_maxd[3] = {0, 0, 0}, cls_maxne[3] = {0, 0, 0};
     int cls_xoff[3][9] = {};                 // per-XCD list offsets inside each class (host copy)
     int wall_khz = 100000;                   // rate of the device wall clock
+    // pinned host staging of a run's read-back (stamps, failure, counters, per-trajectory
+    // statistics, sums): every copy is queued on the run's stream, then one synchronization
+    void* pin = nullptr;
+    size_t pin_bytes = 0;
 };
 
 namespace {
@@ -1182,30 +1186,59 @@ int qtm_run_range(qtm_ctx* c, int64_t traj_begin, int64_t count, uint64_t seed) 
         int rc = enqueue_run(c, a, count, c->stream, &li);
         if (rc) return rc;
     }
+    // read-back: every copy queued on the run's stream into pinned staging, one wait
+    size_t rb = 64;                                   // stamps [2], failure, counters [4]
+    for (auto& S : c->sys) rb += sizeof(int) * 4 * (size_t)count + sizeof(double) * 3 * (size_t)S.n_e * S.n_t;
+    if (rb > c->pin_bytes) {
+        if (c->pin) { (void)hipHostFree(c->pin); c->pin = nullptr; c->pin_bytes = 0; }
+        HIPCHECK(hipHostMalloc(&c->pin, rb, hipHostMallocDefault));
+        c->pin_bytes = rb;
+    }
+    char* hp = (char*)c->pin;
+    HIPCHECK(hipMemcpyAsync(hp, c->d_stamp, 16, hipMemcpyDeviceToHost, c->stream));
+    HIPCHECK(hipMemcpyAsync(hp + 16, c->d_fail, 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHECK(hipMemcpyAsync(hp + 32, c->d_counters, 32, hipMemcpyDeviceToHost, c->stream));
+    {
+        char* q = hp + 64;
+        for (auto& S : c->sys) {
+            const size_t m = (size_t)S.n_e * S.n_t;
+            HIPCHECK(hipMemcpyAsync(q, S.tstat.p, sizeof(int) * 4 * count, hipMemcpyDeviceToHost, c->stream));
+            q += sizeof(int) * 4 * count;
+            HIPCHECK(hipMemcpyAsync(q, S.sum.p, sizeof(double) * 2 * m, hipMemcpyDeviceToHost, c->stream));
+            q += sizeof(double) * 2 * m;
+            HIPCHECK(hipMemcpyAsync(q, S.sumsq.p, sizeof(double) * m, hipMemcpyDeviceToHost, c->stream));
+            q += sizeof(double) * m;
+        }
+    }
     HIPCHECK(hipStreamSynchronize(c->stream));
     // trajectory kernel(s) time from the two device timestamps around them
-    unsigned long long stamps[2] = {0, 0};
-    HIPCHECK(hipMemcpy(stamps, c->d_stamp, sizeof(stamps), hipMemcpyDeviceToHost));
+    unsigned long long stamps[2];
+    std::memcpy(stamps, hp, 16);
     const double ms = (double)(stamps[1] - stamps[0]) / (double)c->wall_khz;
     long long failv = 0;
     unsigned long long ctrs[4];
-    HIPCHECK(hipMemcpy(&failv, c->d_fail, sizeof(long long), hipMemcpyDeviceToHost));
-    HIPCHECK(hipMemcpy(ctrs, c->d_counters, sizeof(ctrs), hipMemcpyDeviceToHost));
+    std::memcpy(&failv, hp + 16, 8);
+    std::memcpy(ctrs, hp + 32, 32);
     // statistics
     qtm_stats_t st{};
     st.ntraj = count;
-    for (auto& S : c->sys) {
-        std::vector<int> ts((size_t)4 * count);
-        HIPCHECK(hipMemcpy(ts.data(), S.tstat.p, sizeof(int) * 4 * count, hipMemcpyDeviceToHost));
-        for (long long q = 0; q < count; ++q) {
-            st.accepted += ts[4 * q]; st.rejected += ts[4 * q + 1]; st.segments += ts[4 * q + 2]; st.jumps += ts[4 * q + 3];
+    {
+        const char* q = hp + 64;
+        for (auto& S : c->sys) {
+            const int* ts = (const int*)q;
+            for (long long i = 0; i < count; ++i) {
+                st.accepted += ts[4 * i]; st.rejected += ts[4 * i + 1]; st.segments += ts[4 * i + 2]; st.jumps += ts[4 * i + 3];
+            }
+            q += sizeof(int) * 4 * count;
+            const size_t m = (size_t)S.n_e * S.n_t;
+            S.h_sum.resize(2 * m);
+            S.h_sumsq.resize(m);
+            std::memcpy(S.h_sum.data(), q, sizeof(double) * 2 * m);
+            q += sizeof(double) * 2 * m;
+            std::memcpy(S.h_sumsq.data(), q, sizeof(double) * m);
+            q += sizeof(double) * m;
+            S.sum_count = count;
         }
-        size_t m = (size_t)S.n_e * S.n_t;
-        S.h_sum.resize(2 * m);
-        S.h_sumsq.resize(m);
-        HIPCHECK(hipMemcpy(S.h_sum.data(), S.sum.p, sizeof(double) * 2 * m, hipMemcpyDeviceToHost));
-        HIPCHECK(hipMemcpy(S.h_sumsq.data(), S.sumsq.p, sizeof(double) * m, hipMemcpyDeviceToHost));
-        S.sum_count = count;
     }
     st.passes = (int64_t)ctrs[0];
     st.max_team_passes = (int64_t)ctrs[2];
@@ -1549,6 +1582,7 @@ void qtm_destroy(qtm_ctx* c) {
     for (auto e : c->side_ev) if (e) (void)hipEventDestroy(e);
     for (auto st : c->side) if (st) (void)hipStreamDestroy(st);
     if (c->fork) (void)hipEventDestroy(c->fork);
+    if (c->pin) (void)hipHostFree(c->pin);
     delete c;
 }
 
