@@ -96,8 +96,15 @@ typedef struct {
                                  of the tile classes d <= 64, 128, 256, one of
                                  qtm_batch_tile_candidates(class) (0: the class's default shape;
                                  -1: the class runs on the sliced-ELL SpMM kernel instead) */
-    int32_t reserved[1];
+    int32_t chunk_traj;       /* runs that keep no per-trajectory data (keep_traj, record_jumps and
+                                 seg_cap all 0): at most this many trajectories per chunk (0: as many
+                                 as QTM_RUN_CHUNK_MB of expectation samples hold) */
 } qtm_opts;
+
+/* Device memory for the per-trajectory expectation samples of one chunk of a run that
+ * keeps no per-trajectory data: a run of more trajectories than that processes them in
+ * chunks of consecutive indices and adds the chunks' FP64 sums in chunk order. */
+#define QTM_RUN_CHUNK_MB 2048
 
 /* Integrators.  QTM_INT_DOPRI5: adaptive Dormand-Prince 5(4) with dense output (the
  * default; every form).  QTM_INT_EXPO: the exact propagator for stiff problems --
@@ -211,7 +218,10 @@ int qtm_create_batch(qtm_ctx** out, int32_t n_sys, const qtm_system* sys, const 
  * Errors: QTM_E_INVAL (ntraj < 1), QTM_E_NOMEM, QTM_E_DEVICE, QTM_E_STEP (one
  * or more trajectories failed -- the analogue of the negative solver status the
  * paper's solver wrapper reports, Sec. 3; qtm_stats names the smallest index;
- * averages are then not available). */
+ * averages are then not available).  A context with keep_traj, record_jumps and
+ * seg_cap all 0 runs more trajectories than one chunk holds (chunk_traj, else
+ * QTM_RUN_CHUNK_MB of samples) chunk after chunk, so device memory stays bounded
+ * whatever ntraj is; the averages then add the chunks' sums in chunk order. */
 int qtm_run(qtm_ctx* ctx, int64_t ntraj, uint64_t seed);
 
 /* Runs trajectories traj_begin .. traj_begin+count-1 (traj_begin >= 0,

@@ -51,7 +51,7 @@ class _Opts(C.Structure):
                 ("max_steps", C.c_int64), ("device", C.c_int32), ("record_jumps", C.c_int32),
                 ("stream", C.c_void_p), ("keep_traj", C.c_int32), ("seg_cap", C.c_int32),
                 ("tile_cols", C.c_int32), ("team_waves", C.c_int32), ("integrator", C.c_int32),
-                ("expo_substeps", C.c_int32), ("class_waves", C.c_int32 * 3), ("reserved", C.c_int32 * 1)]
+                ("expo_substeps", C.c_int32), ("class_waves", C.c_int32 * 3), ("chunk_traj", C.c_int32)]
 
 
 class _Stats(C.Structure):
@@ -198,6 +198,7 @@ class Opts:
     integrator: int = INT_DOPRI5
     expo_substeps: int = 0
     class_waves: tuple = (0, 0, 0)     # batched tile classes d <= 64, 128, 256: waves per team (0: default)
+    chunk_traj: int = 0                # runs keeping no per-trajectory data: trajectories per chunk (0: budget)
     stream: Optional[int] = None      # raw hipStream_t; None: torch's current stream when available
 
     def _c(self) -> _Opts:
@@ -210,6 +211,7 @@ class Opts:
         o.integrator, o.expo_substeps = self.integrator, self.expo_substeps
         for k in range(3):
             o.class_waves[k] = int(self.class_waves[k])
+        o.chunk_traj = int(self.chunk_traj)
         st = self.stream
         if st is None:
             try:

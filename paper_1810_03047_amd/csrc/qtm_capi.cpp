@@ -829,6 +829,7 @@ static int create_common(qtm_ctx** out, int32_t n_sys, const qtm_system* sys, co
     if (opt.max_steps < 1) return fail(QTM_E_INVAL, "max_steps must be >= 1");
     if (opt.record_jumps < 0 || opt.seg_cap < 0) return fail(QTM_E_INVAL, "negative capacity");
     if (opt.team_waves < 0 || opt.tile_cols < 0) return fail(QTM_E_INVAL, "negative tile option");
+    if (opt.chunk_traj < 0) return fail(QTM_E_INVAL, "negative chunk_traj");
     for (int k = 0; k < 3; ++k) {
         if (opt.class_waves[k] == 0 || opt.class_waves[k] == -1) continue;
         int w[8];
@@ -1112,10 +1113,64 @@ static qtm::RunArgs run_args(const qtm_ctx* c, long long count, int jcap, int se
     return a;
 }
 
+static int run_range_one(qtm_ctx* c, int64_t traj_begin, int64_t count, uint64_t seed);
+
+// A run of more trajectories than one chunk holds: chunks of consecutive indices, each a
+// complete run, their FP64 sums added on the host in chunk order and their statistics summed.
+static int run_chunked(qtm_ctx* c, int64_t traj_begin, int64_t count, uint64_t seed, long long chunk) {
+    auto t0 = std::chrono::steady_clock::now();
+    std::vector<std::vector<double>> ts(c->sys.size()), tq(c->sys.size());
+    qtm_stats_t acc{};
+    for (long long done = 0; done < count; done += chunk) {
+        const long long n = std::min<long long>(chunk, count - done);
+        const int rc = run_range_one(c, traj_begin + done, n, seed);
+        if (rc) return rc;
+        const qtm_stats_t& s = c->st;
+        acc.accepted += s.accepted; acc.rejected += s.rejected; acc.segments += s.segments; acc.jumps += s.jumps;
+        acc.rhs_evals += s.rhs_evals; acc.passes += s.passes; acc.root_evals += s.root_evals;
+        acc.kernel_ms += s.kernel_ms;
+        acc.max_team_passes = std::max(acc.max_team_passes, s.max_team_passes);
+        acc.blocks = s.blocks; acc.threads = s.threads; acc.tile_cols = s.tile_cols; acc.lds_bytes = s.lds_bytes;
+        acc.team_shape = s.team_shape;
+        for (size_t i = 0; i < c->sys.size(); ++i) {
+            const SysHost& S = c->sys[i];
+            if (done == 0) { ts[i] = S.h_sum; tq[i] = S.h_sumsq; continue; }
+            for (size_t j = 0; j < ts[i].size(); ++j) ts[i][j] += S.h_sum[j];
+            for (size_t j = 0; j < tq[i].size(); ++j) tq[i][j] += S.h_sumsq[j];
+        }
+    }
+    for (size_t i = 0; i < c->sys.size(); ++i) {
+        c->sys[i].h_sum = ts[i];
+        c->sys[i].h_sumsq = tq[i];
+        c->sys[i].sum_count = count;
+    }
+    acc.ntraj = count;
+    acc.failed_traj = -1;
+    acc.elapsed_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    c->st = acc;
+    c->last_begin = traj_begin;
+    c->last_count = count;
+    return QTM_OK;
+}
+
 int qtm_run_range(qtm_ctx* c, int64_t traj_begin, int64_t count, uint64_t seed) {
     if (check_ctx(c)) return QTM_E_INVAL;
     if (count < 1 || traj_begin < 0) return fail(QTM_E_INVAL, "need count >= 1 and traj_begin >= 0");
     if ((c->o.form & QTM_FORM_LEARNED) && !c->have_mlp) return fail(QTM_E_STATE, "learned form requested before qtm_set_proposal");
+    if (!c->o.keep_traj && c->o.record_jumps == 0 && c->o.seg_cap == 0) {
+        // no per-trajectory data is kept: the samples of one chunk bound the device memory
+        size_t per_traj = 0;
+        for (auto& S : c->sys) per_traj += sizeof(double2) * (size_t)S.n_e * S.n_t;
+        long long chunk = (long long)(((size_t)QTM_RUN_CHUNK_MB << 20) / std::max<size_t>(per_traj, 1));
+        if (c->o.chunk_traj > 0) chunk = std::min<long long>(chunk, c->o.chunk_traj);
+        chunk = std::max(chunk, 1LL);
+        if (count > chunk) return run_chunked(c, traj_begin, count, seed, chunk);
+    }
+    return run_range_one(c, traj_begin, count, seed);
+}
+
+// One run of count trajectories (every per-trajectory buffer sized for count).
+static int run_range_one(qtm_ctx* c, int64_t traj_begin, int64_t count, uint64_t seed) {
     HIPCHECK(hipSetDevice(c->device));
     auto t0 = std::chrono::steady_clock::now();
     c->ran = false;

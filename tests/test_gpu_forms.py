@@ -76,6 +76,20 @@ def test_sparse_tfim_full_size_sampled():
         assert np.max(np.abs(X[i] - r["X"][0])) <= 1e-8
 
 
+@pytest.mark.parametrize("cols", [1, 2])
+def test_sparse_wide_blocks_fp64_exact(cols):
+    """512 < d <= 1024 runs on 512-thread blocks (two rows per thread, two waves per
+    SIMD); one and two trajectories per block, trajectory by trajectory against the
+    oracle (Ising chain L = 10, d = 1024)."""
+    s = w.tfim(t_end=4.0, n_t=41)
+    n = 40
+    ctx = _gpu(s, n, seed=6, tile_cols=cols)
+    st = ctx.stats()
+    assert st["threads"] == 512 and st["tile_cols"] == cols, st
+    r = oracle.run(s, n, seed=6, jcap=32)
+    print(f"tfim L=10 wide blocks, {cols} trajectories per block:", _exact(ctx, r, n))
+
+
 def test_sparse_fp32_products_statistical():
     s = w.tfim(L=6, t_end=5.0, n_t=26)
     n = 3000

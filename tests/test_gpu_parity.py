@@ -111,6 +111,39 @@ def test_batched_persistent_equals_plain():
     assert np.array_equal(a["X"], b["X"])
 
 
+def test_chunked_run_equals_single_run():
+    """A run that keeps no per-trajectory data goes chunk by chunk when it holds more
+    trajectories than a chunk: the same trajectories (same statistics) and the same
+    sums up to the order of the FP64 additions."""
+    s = w.jaynes_cummings(N=6, t_end=4.0, n_t=41)
+    n = 100
+    print(f"[gpu] chunked run jcm N=6 n={n}", flush=True)
+    res = {}
+    for chunk in (0, 7, 33):
+        ctx = qtm.create_system(s, qtm.Opts(chunk_traj=chunk))
+        ctx.run(n, 5)
+        st = ctx.stats()
+        sums = ctx.sums()
+        mean, var = ctx.expect()
+        ctx.destroy()
+        res[chunk] = (st, sums, mean, var)
+    st0, (s0, q0, c0), m0, v0 = res[0]
+    for chunk in (7, 33):
+        st, (s1, q1, c1), m1, v1 = res[chunk]
+        assert c1 == c0 == n
+        for k in ("accepted", "rejected", "segments", "jumps"):       # per-trajectory statistics
+            assert st[k] == st0[k], (chunk, k)
+        assert st["ntraj"] == n and st["failed_traj"] == -1
+        assert np.allclose(s1, s0, rtol=1e-13, atol=1e-13), chunk
+        assert np.allclose(q1, q0, rtol=1e-13, atol=1e-13), chunk
+        assert np.allclose(m1, m0, rtol=1e-13, atol=1e-13), chunk
+    # a context that keeps per-trajectory data never chunks
+    ctx = qtm.create_system(s, qtm.Opts(chunk_traj=7, keep_traj=1))
+    ctx.run(n, 5)
+    assert ctx.traj_expect().shape[0] == n
+    ctx.destroy()
+
+
 def test_failure_path_max_steps():
     s = w.two_level()
     ctx = qtm.create_system(s, qtm.Opts(max_steps=3))
