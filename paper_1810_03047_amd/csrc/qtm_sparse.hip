@@ -110,12 +110,29 @@ template <int R, int C, int P> const void* sparse_fn_wide();
 int launch_sparse(const RunArgs& a0, const DevSystem& s0, int max_d, long long max_ell, int prec, int cols,
                   hipStream_t st, LaunchInfo* info) {
     RunArgs a = a0;
-    // 512 < d <= 1024: wide blocks, two rows per thread and at most two trajectories per
-    // block (Ising chain L = 10, d = 1024: 691 ms against 748 in FP32, 1,202 against
-    // 1,293 in FP64); at d <= 512 the 256-thread blocks stay faster
+    // Block size.  The registers allow one wave per SIMD (four per CU) at up to four rows
+    // per thread, so for d <= 512 the block is as small as four rows per thread allow: the
+    // same waves per CU in more, smaller blocks, whose barriers and reductions span fewer
+    // waves (trilinear d = 512: 38 ms against 54 with 256-thread blocks; Ising d = 256:
+    // 40 against 72; dense d = 200: 52 against 72, FP32).  512 < d <= 1024: wide blocks,
+    // two rows per thread and at most two trajectories per block, two waves per SIMD
+    // (Ising d = 1024, where the ELL in LDS leaves one block per CU: 691 ms against 748
+    // in FP32, 1,202 against 1,293 in FP64).  Beyond: 256 threads, up to eight rows.
+    // A launch with too few trajectories to occupy the small blocks (about four single-wave
+    // blocks per CU) is latency bound: the block grows back towards 256 threads, more
+    // threads per trajectory (the per-system launches of a batch's plain form, 500 each).
     const bool wide = max_d > 2 * kSparseThreads && max_d <= 4 * kSparseThreads;
     if (wide && cols > 2) cols = 2;
-    const int threads = wide ? 2 * kSparseThreads : max_d >= kSparseThreads ? kSparseThreads : ((max_d + 63) / 64) * 64;
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return -3;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return -3;
+    int threads = wide ? 2 * kSparseThreads
+                       : max_d > 2 * kSparseThreads ? kSparseThreads
+                                                    : std::max(64, ((max_d + 3) / 4 + 63) / 64 * 64);
+    if (!wide && threads < kSparseThreads) {
+        const long long total = s0.count * (long long)std::max(1, a.n_sys);
+        while (threads < kSparseThreads && total < (long long)ncu * (kSparseThreads / threads) * cols) threads *= 2;
+    }
     int rpt = (max_d + threads - 1) / threads;
     if (rpt == 3) rpt = 4;
     if (rpt > 4 && rpt <= 8) rpt = 8;
@@ -124,9 +141,6 @@ int launch_sparse(const RunArgs& a0, const DevSystem& s0, int max_d, long long m
     while (rpt * cols > 8) cols >>= 1;
     size_t lds = (((size_t)cols * sizeof(Col) + 15) & ~(size_t)15) + (size_t)max_d * cols * sizeof(double2) +
                  (size_t)(threads / 64) * cols * kNVMax * sizeof(double);
-    int dev = 0, ncu = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return -3;
-    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return -3;
     const void* fn = nullptr;
 #define QTM_SPARSE_CASE(R, C) \
     if (rpt == R && cols == C) fn = prec == 0 ? sparse_fn_inst<R, C, 0>() : sparse_fn_inst<R, C, 1>();
