@@ -1471,14 +1471,17 @@ int qtm_train_proposal(qtm_ctx* c, const float* feat, const float* tgt, int64_t 
         c->have_mlp = true;
     }
     DevScratch sc;
-    float *dF, *dT, *dMaster, *dWork, *dM, *dV, *dPart, *dLp, *dG, *dL;
+    float *dF, *dT, *dMaster, *dWork, *dM, *dV, *dPart, *dLp, *dL;
     int* dPerm;
     int nblk = qtm::mlp_partial_rows(batch);
+    // one loss per step of an epoch, read back once per epoch (no wait between steps)
+    const int64_t steps_ep = n < batch ? 1 : n / batch;
     if (sc.get(&dF, (size_t)n * qtm::kNF) || sc.get(&dT, (size_t)n * 3) || sc.get(&dMaster, qtm::kNTotal) ||
         sc.get(&dWork, qtm::kNTotal) || sc.get(&dM, qtm::kNParam) || sc.get(&dV, qtm::kNParam) ||
-        sc.get(&dPart, (size_t)nblk * qtm::kNParam) || sc.get(&dLp, nblk) || sc.get(&dG, qtm::kNParam) ||
-        sc.get(&dL, 1) || sc.get(&dPerm, (size_t)n))
+        sc.get(&dPart, (size_t)nblk * qtm::kNParam) || sc.get(&dLp, nblk) ||
+        sc.get(&dL, (size_t)steps_ep) || sc.get(&dPerm, (size_t)n))
         return fail(QTM_E_NOMEM, "device allocation failed");
+    std::vector<float> hl((size_t)steps_ep);
     std::vector<float> q;
     working_copy(c->mlp_master, q);
     HIPCHECK(hipMemcpy(dF, feat, sizeof(float) * n * qtm::kNF, hipMemcpyHostToDevice));
@@ -1496,20 +1499,20 @@ int qtm_train_proposal(qtm_ctx* c, const float* feat, const float* tgt, int64_t 
         for (int64_t i = n - 1; i > 0; --i) std::swap(perm[i], perm[next() % (uint64_t)(i + 1)]);
         HIPCHECK(hipMemcpy(dPerm, perm.data(), sizeof(int) * n, hipMemcpyHostToDevice));
         double esum = 0.0;
-        int64_t eseen = 0;
+        int64_t eseen = 0, k = 0;
+        std::vector<int> nbs;
         for (int64_t b0 = 0; b0 + batch <= n || (b0 == 0 && n < batch); b0 += batch) {
             int nb = (int)std::min<int64_t>(batch, n - b0);
-            if (qtm::launch_mlp_grad(dWork, dF, dT, dPerm, b0, nb, dPart, dLp, dG, dL, c->stream))
-                return fail(QTM_E_DEVICE, "gradient kernel launch failed");
-            if (qtm::launch_mlp_adam(dMaster, dWork, dG, dM, dV, lr, ++step, c->stream))
-                return fail(QTM_E_DEVICE, "adam kernel launch failed");
-            float l = 0.f;
-            HIPCHECK(hipMemcpyAsync(&l, dL, sizeof(float), hipMemcpyDeviceToHost, c->stream));
-            HIPCHECK(hipStreamSynchronize(c->stream));
-            esum += (double)l * nb;
-            eseen += nb;
+            if (qtm::launch_mlp_train_step(dMaster, dWork, dM, dV, dF, dT, dPerm, b0, nb, dPart, dLp, dL + k, lr, ++step,
+                                           c->stream))
+                return fail(QTM_E_DEVICE, "training step launch failed");
+            nbs.push_back(nb);
+            ++k;
             if (n < batch) break;
         }
+        HIPCHECK(hipMemcpyAsync(hl.data(), dL, sizeof(float) * k, hipMemcpyDeviceToHost, c->stream));
+        HIPCHECK(hipStreamSynchronize(c->stream));
+        for (int64_t i = 0; i < k; ++i) { esum += (double)hl[i] * nbs[i]; eseen += nbs[i]; }
         if (loss_out) loss_out[ep] = (float)(esum / (double)std::max<int64_t>(1, eseen));
     }
     HIPCHECK(hipMemcpy(c->mlp_master.data(), dMaster, sizeof(float) * qtm::kNTotal, hipMemcpyDeviceToHost));

@@ -120,7 +120,10 @@ int dense_occupancy(int max_d, int prec, int tile_cols, int* blocks_per_cu, int*
 // proposal network (qtm_mlp.hip)
 int launch_mlp_grad(const float* P, const float* feat, const float* tgt, const int* perm, long long base, int n,
                     float* partial, float* loss_part, float* grad, float* loss, hipStream_t st);
-int launch_mlp_adam(float* master, float* work, const float* grad, float* m, float* v, float lr, int step, hipStream_t st);
+// one training step: gradient of the batch, then Adam on the masters and the BF16-valued copy
+int launch_mlp_train_step(float* master, float* work, float* m, float* v, const float* feat, const float* tgt,
+                          const int* perm, long long base, int n, float* partial, float* loss_part, float* loss, float lr,
+                          int step, hipStream_t st);
 int mlp_partial_rows(int n);
 // wave-per-tile dense kernel (qtm_wave.hip), d <= 64
 int wave_supported(int d);
