@@ -50,15 +50,6 @@ __device__ __forceinline__ void wave_sync() {
 
 constexpr int kXV = 8;       // values per column in one team reduction
 
-// [theta^i] of the dense-output weights c_a(theta) = (1, th, th(1-th), th^2(1-th), th^2(1-th)^2)
-__device__ __forceinline__ constexpr double dense_coef(int a, int i) {
-    return a == 0 ? (i == 0 ? 1.0 : 0.0)
-         : a == 1 ? (i == 1 ? 1.0 : 0.0)
-         : a == 2 ? (i == 1 ? 1.0 : i == 2 ? -1.0 : 0.0)
-         : a == 3 ? (i == 2 ? 1.0 : i == 3 ? -1.0 : 0.0)
-         : (i == 2 ? 1.0 : i == 3 ? -2.0 : i == 4 ? 1.0 : 0.0);
-}
-
 // LEARN = false compiles out the segment-start features and the proposal network
 // (kernels that never run the learned form or record segments).  TD = true adds the
 // time-dependent terms of the Hamiltonian: every product is M W + sum_k M_k (f_k(t_s) W)
@@ -944,95 +935,90 @@ struct Team {
         }
     }
 
-    // The five coefficient vectors of the dense output of element e, in FP64:
-    // v = {y, D, B, R4, R5} with u(th) = sum_a c_a(th) v_a, c = (1, th, th(1-th), th^2(1-th), th^2(1-th)^2)
-    QTM_DI void dense_vectors(int e, double2 (&v)[5]) const {
-        v[0] = y[e];
-        v[1] = csub(yn[e], y[e]);
-        v[2] = csub(cscale(h, to_d2(k[0][e])), v[1]);
-        v[3] = csub(csub(v[1], cscale(h, to_d2(k[6][e]))), v[2]);
-        v[4] = cscale(h, cfma(dp_d(6), to_d2(k[6][e]), to_d2(ds[e])));
+    // The dense output of element e as a polynomial in th, in FP64: u(th) = sum_k th^k w_k.
+    // From u = y + th D + th(1-th) B + th^2(1-th) R4 + th^2(1-th)^2 R5 (D = yn - y,
+    // B = h k1 - D, R4 = D - h k7 - B, R5 = h sum_j d_j k_j):
+    // w = {y, D + B, R4 + R5 - B, -(R4 + 2 R5), R5}
+    QTM_DI void dense_monomials(int e, double2 (&w)[5]) const {
+        const double2 D = csub(yn[e], y[e]);
+        const double2 B = csub(cscale(h, to_d2(k[0][e])), D);
+        const double2 R4 = csub(csub(D, cscale(h, to_d2(k[6][e]))), B);
+        const double2 R5 = cscale(h, cfma(dp_d(6), to_d2(k[6][e]), to_d2(ds[e])));
+        w[0] = y[e];
+        w[1] = cadd(D, B);
+        w[2] = csub(cadd(R4, R5), B);
+        w[3] = make_double2(-(R4.x + 2.0 * R5.x), -(R4.y + 2.0 * R5.y));
+        w[4] = R5;
     }
 
-    // Gram matrices of the dense output, reduced over the team, for the lanes with on set:
-    // G[0][ab] = Re <v_a, v_b> and G[1 + j][ab] = Re <v_a, O_j v_b> for the NO real
-    // diagonal observables O_j (upper triangle a <= b, 15 values each).  Then
-    // <u(th)|O|u(th)> = sum_ab c_a(th) c_b(th) G[.][ab] for every th of the step.
-    template <int NO> QTM_DI void gram_sums(bool on, double (&G)[NO + 1][15]) {
+    // Coefficients of the degree-8 polynomials <u(th)|u(th)> (P[0]) and <u(th)|O_j|u(th)>
+    // (P[1 + j], the NO real diagonal observables O_j), reduced over the team, for the lanes
+    // with on set: P[o][m] = sum over k + l = m of Re <w_k, O w_l> (both orders).  Every
+    // output time of the step and the jump time's norm come from these 9 (NO + 1) sums.
+    template <int NO> QTM_DI void poly_sums(bool on, double (&P)[NO + 1][9]) {
 #pragma unroll
         for (int o = 0; o <= NO; ++o)
 #pragma unroll
-            for (int n = 0; n < 15; ++n) G[o][n] = 0.0;
+            for (int m = 0; m < 9; ++m) P[o][m] = 0.0;
         if (on) {
             const int qb = qbase();
 #pragma unroll
             for (int e = 0; e < NE; ++e) {
                 const int q = qb + cst(e);
                 if (q >= d) continue;
-                double2 v[5];
-                dense_vectors(e, v);
-                double w[NO];
+                double2 w[5];
+                dense_monomials(e, w);
+                double o1[NO > 0 ? NO : 1], o2[NO > 0 ? NO : 1];
 #pragma unroll
-                for (int j = 0; j < NO; ++j) w[j] = Od[(size_t)j * d + q].x;
-                int n = 0;
+                for (int jo = 0; jo < NO; ++jo) { o1[jo] = Od[(size_t)jo * d + q].x; o2[jo] = 2.0 * o1[jo]; }
 #pragma unroll
                 for (int a = 0; a < 5; ++a)
 #pragma unroll
                     for (int b = a; b < 5; ++b) {
-                        const double pab = v[a].x * v[b].x + v[a].y * v[b].y;
-                        G[0][n] += pab;
+                        const double pab = w[a].x * w[b].x + w[a].y * w[b].y;
+                        if (a == b) P[0][a + b] += pab;
+                        else P[0][a + b] = fma(2.0, pab, P[0][a + b]);
 #pragma unroll
-                        for (int j = 0; j < NO; ++j) G[1 + j][n] = fma(w[j], pab, G[1 + j][n]);
-                        ++n;
+                        for (int jo = 0; jo < NO; ++jo) P[1 + jo][a + b] = fma(a == b ? o1[jo] : o2[jo], pab, P[1 + jo][a + b]);
                     }
             }
         }
         // team reductions of kXV values at a time
-        constexpr int NV = (NO + 1) * 15;
+        constexpr int NV = (NO + 1) * 9;
 #pragma unroll
         for (int c0 = 0; c0 < NV; c0 += kXV) {
             double tmp[kXV];
 #pragma unroll
-            for (int i = 0; i < kXV; ++i) tmp[i] = c0 + i < NV ? G[(c0 + i) / 15][(c0 + i) % 15] : 0.0;
+            for (int i = 0; i < kXV; ++i) tmp[i] = c0 + i < NV ? P[(c0 + i) / 9][(c0 + i) % 9] : 0.0;
             tsum<kXV>(tmp);
 #pragma unroll
             for (int i = 0; i < kXV; ++i)
-                if (c0 + i < NV) G[(c0 + i) / 15][(c0 + i) % 15] = tmp[i];
+                if (c0 + i < NV) P[(c0 + i) / 9][(c0 + i) % 9] = tmp[i];
         }
     }
 
-    // sum_ab c_a(th) c_b(th) g[ab] over the upper triangle, with the weights
-    // wq[ab] = c_a c_b (a == b) or 2 c_a c_b (a < b)
-    QTM_DI static double gram_at(const double (&g)[15], const double (&wq)[15]) {
-        double v = 0.0;
+    QTM_DI static double horner8(const double (&p)[9], double x) {
+        double v = p[8];
 #pragma unroll
-        for (int n = 0; n < 15; ++n) v = fma(wq[n], g[n], v);
+        for (int m = 7; m >= 0; --m) v = fma(v, x, p[m]);
         return v;
     }
 
-    // Outputs inside the step from the Gram matrices: each lane evaluates its own output
-    // times, t < t_k <= t + h (accepted step; t_k = t + h from y_new) or t < t_k < t*
-    // (jump step), as quadratic forms in th; no team reduction per output time
-    template <int NO> QTM_DI void outputs_gram(bool on, const double (&G)[NO + 1][15]) {
+    // Outputs inside the step from the polynomials: each lane evaluates its own output
+    // times, t < t_k <= t + h (accepted step; t_k = t + h from th = 1) or t < t_k < t*
+    // (jump step); no team reduction per output time
+    template <int NO> QTM_DI void outputs_poly(bool on, const double (&P)[NO + 1][9]) {
         const bool acc = action == ACT_ACCEPT, jmp = action == ACT_JUMP;
         while (on) {
             const double tk = tnext;
             const bool out = kk < S.n_t && ((acc && tk <= tb) || (jmp && tk < tb));
             if (!out) break;
             const double th = (acc && tk == tb) ? 1.0 : (tk - t) / h;
-            const double t1 = 1.0 - th;
-            const double c[5] = {1.0, th, th * t1, th * th * t1, th * th * t1 * t1};
-            double wq[15];                      // weights of the quadratic form, shared by all values
-            int n = 0;
-#pragma unroll
-            for (int a = 0; a < 5; ++a)
-#pragma unroll
-                for (int b = a; b < 5; ++b) wq[n++] = (a == b ? c[a] : 2.0 * c[a]) * c[b];
-            const double inn = 1.0 / gram_at(G[0], wq);
+            const double inn = 1.0 / horner8(P[0], th);
             if (lg == 0 && wv == 0) {
 #pragma unroll
-                for (int j = 0; j < NO; ++j)
-                    S.X[((size_t)traj * S.n_e + j) * S.n_t + kk] = make_double2(gram_at(G[1 + j], wq) * inn, 0.0);
+                for (int jo = 0; jo < NO; ++jo)
+                    S.X[((size_t)traj * S.n_e + jo) * S.n_t + kk] = make_double2(horner8(P[1 + jo], th) * inn, 0.0);
             }
             kk++;
             tnext = tnext2;
@@ -1040,33 +1026,12 @@ struct Team {
         }
     }
 
-    // jump time of the lanes with action ACT_JUMP from the reduced Gram matrix of the norm
-    QTM_DI void jump_root(const double (&g)[15]) {
+    // Jump time of the lanes with action ACT_JUMP: the first th in [0, 1] where the
+    // degree-8 norm polynomial p reaches r -- a 32-point scan for the first sign change,
+    // then bisection to 1e-13
+    QTM_DI void jump_root(const double (&p)[9]) {
         if (action == ACT_JUMP) {
-            // ||u(theta)||^2 as a degree-8 polynomial: P_k = sum_{a<=b} w_ab G_ab [theta^k] c_a c_b
-            double P[9];
-#pragma unroll
-            for (int k2 = 0; k2 < 9; ++k2) P[k2] = 0.0;
-            int n = 0;
-#pragma unroll
-            for (int a = 0; a < 5; ++a)
-#pragma unroll
-                for (int b = a; b < 5; ++b) {
-#pragma unroll
-                    for (int i = 0; i < 5; ++i)
-#pragma unroll
-                        for (int j = 0; j < 5; ++j) {
-                            const double cij = dense_coef(a, i) * dense_coef(b, j);
-                            if (cij != 0.0) P[i + j] = fma((a == b ? 1.0 : 2.0) * cij, g[n], P[i + j]);
-                        }
-                    ++n;
-                }
-            auto f = [&](double x) {
-                double v = P[8];
-#pragma unroll
-                for (int k2 = 7; k2 >= 0; --k2) v = fma(v, x, P[k2]);
-                return v - r;
-            };
+            auto f = [&](double x) { return horner8(p, x) - r; };
             double lo = 0.0, hi = 1.0;
             int nev = 0;
             for (int m = 1; m <= 32; ++m) {
@@ -1086,52 +1051,18 @@ struct Team {
         }
     }
 
-    // Jump time: first theta in [0,1] with ||u(theta)||^2 = r, from the Gram matrix of
-    // v = {y, D, B, R4, R5}: u = sum_p c_p v_p, c = (1, th, th(1-th), th^2(1-th), th^2(1-th)^2)
+    // Jump time for the other output paths: the norm polynomial alone
     QTM_DI void jump_time() {
-        const bool on = action == ACT_JUMP;
-        double g[15];
-#pragma unroll
-        for (int n = 0; n < 15; ++n) g[n] = 0.0;
-        if (on) {
-#pragma unroll
-            for (int e = 0; e < NE; ++e) {
-                int q = comp(e);
-                if (q < 0) continue;
-                double2 v[5];
-                dense_vectors(e, v);
-                int n = 0;
-#pragma unroll
-                for (int a = 0; a < 5; ++a)
-#pragma unroll
-                    for (int b = a; b < 5; ++b) {
-                        g[n] += v[a].x * v[b].x + v[a].y * v[b].y;
-                        ++n;
-                    }
-            }
-        }
-        {
-            // two team reductions of at most kXV values
-            double g0[8], g1[7];
-#pragma unroll
-            for (int n = 0; n < 8; ++n) g0[n] = g[n];
-#pragma unroll
-            for (int n = 0; n < 7; ++n) g1[n] = g[8 + n];
-            tsum<8>(g0);
-            tsum<7>(g1);
-#pragma unroll
-            for (int n = 0; n < 8; ++n) g[n] = g0[n];
-#pragma unroll
-            for (int n = 0; n < 7; ++n) g[8 + n] = g1[n];
-        }
-        jump_root(g);
+        double P[1][9];
+        poly_sums<0>(action == ACT_JUMP, P);
+        jump_root(P[0]);
     }
 
     template <int NO> QTM_DI void gram_outputs(bool need) {
-        double G[NO + 1][15];
-        gram_sums<NO>(need, G);
-        jump_root(G[0]);
-        outputs_gram<NO>(need, G);
+        double P[NO + 1][9];
+        poly_sums<NO>(need, P);
+        jump_root(P[0]);
+        outputs_poly<NO>(need, P);
     }
 
     // this lane's part of ||C_n psi*||^2 (psi* staged), before the team reduction
