@@ -800,6 +800,15 @@ struct Team {
                         inc.x = fmaf((float)cf[j], kj.x, inc.x);
                         inc.y = fmaf((float)cf[j], kj.y, inc.y);
                     }
+                if constexpr (s != 6) {
+                    // a stage input only feeds the FP32 products: y rounded to FP32 plus the
+                    // FP32 increment (y_new, the last stage input, is formed in FP64 below)
+                    w[e] = from_d2<kv_t>(make_double2(0.0, 0.0));
+                    float2& wf = (float2&)w[e];
+                    wf.x = (float)y[e].x + inc.x;
+                    wf.y = (float)y[e].y + inc.y;
+                    continue;
+                }
                 acc = make_double2(y[e].x + (double)inc.x, y[e].y + (double)inc.y);
             }
             if constexpr (s == 6) {
