@@ -926,6 +926,20 @@ struct Body {
 #pragma unroll
             for (int j = 0; j < 6; ++j) cf[j] = (st == ST_STEP) ? h * dp_a(s, j) : 0.0;
             if (s == 1 && st == ST_NEEDF1) cf[0] = cs[gc].h0;
+            if constexpr (std::is_same<kv_t, float2>::value && s != 6) {
+                // FP32 products: a stage input only feeds them, so it is y rounded to FP32
+                // plus the FP32 increment (y_new, the last stage input, is formed in FP64)
+                float ix = 0.f, iy = 0.f;
+#pragma unroll
+                for (int j = 0; j < s; ++j)
+                    if (dp_a(s, j) != 0.0 || (s == 1 && j == 0)) {
+                        const float2 kj = (const float2&)k[j][e];
+                        ix = fmaf((float)cf[j], kj.x, ix);
+                        iy = fmaf((float)cf[j], kj.y, iy);
+                    }
+                W[e] = make_double2((double)((float)y[e].x + ix), (double)((float)y[e].y + iy));
+                continue;
+            }
             double2 acc = y[e];
 #pragma unroll
             for (int j = 0; j < s; ++j)
