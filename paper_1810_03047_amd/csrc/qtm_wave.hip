@@ -919,9 +919,9 @@ struct Team {
         }
         const bool anyj = team_any(action == ACT_JUMP);
         if (NWT == 1 && od_lds == 2 && S.n_e <= 2) {
-            // real diagonal observables: one Gram pass per step serves the jump time and
-            // every output time of every lane (the lanes' own Gram matrices: a trajectory's
-            // results do not depend on its wave neighbours)
+            // real diagonal observables: one pass of norm polynomials per step serves the
+            // jump time and every output time of every lane (each lane's own polynomials: a
+            // trajectory's results do not depend on its wave neighbours)
             const bool need = action == ACT_JUMP || (action == ACT_ACCEPT && kk < S.n_t && tnext <= tb);
             if (team_any(need)) {
                 if (S.n_e == 1) gram_outputs<1>(need);
