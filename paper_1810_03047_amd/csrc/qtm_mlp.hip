@@ -233,21 +233,28 @@ __device__ __forceinline__ float bf16r(float x) {
 
 // One training step's update: the batch gradient (partial rows summed in block order,
 // scaled by 1/batch), then Adam on the FP32 masters and the BF16-valued working copy of
-// the weights.
-__global__ void mlp_reduce_adam_kernel(const float* __restrict__ partial, const float* __restrict__ loss_part, int nblk,
-                                       float inv_n, float* __restrict__ loss, float* __restrict__ master,
-                                       float* __restrict__ work, float* __restrict__ m, float* __restrict__ v, float lr,
-                                       float b1, float b2, float eps, float c1, float c2) {
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p == 0) {
+// the weights.  Four threads per parameter each sum a quarter of the rows (rows r with
+// r % 4 == their part), combined in part order: the result does not depend on scheduling.
+constexpr int kRedParts = 4, kRedThreads = 256, kRedParams = kRedThreads / kRedParts;
+__global__ void __launch_bounds__(kRedThreads) mlp_reduce_adam_kernel(
+        const float* __restrict__ partial, const float* __restrict__ loss_part, int nblk, float inv_n,
+        float* __restrict__ loss, float* __restrict__ master, float* __restrict__ work, float* __restrict__ m,
+        float* __restrict__ v, float lr, float b1, float b2, float eps, float c1, float c2) {
+    __shared__ float part[kRedParts][kRedParams];
+    const int lp = threadIdx.x % kRedParams, k = threadIdx.x / kRedParams;
+    const int p = blockIdx.x * kRedParams + lp;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
         float L = 0.f;
         for (int b = 0; b < nblk; ++b) L += loss_part[b];
         *loss = L * inv_n;
     }
-    if (p >= kNParam) return;
     float g = 0.f;
-    for (int b = 0; b < nblk; ++b) g += partial[(size_t)b * kNParam + p];
-    g *= inv_n;
+    if (p < kNParam)
+        for (int b = k; b < nblk; b += kRedParts) g += partial[(size_t)b * kNParam + p];
+    part[k][lp] = g;
+    __syncthreads();
+    if (k != 0 || p >= kNParam) return;
+    g = ((part[0][lp] + part[1][lp]) + (part[2][lp] + part[3][lp])) * inv_n;
     float mm = b1 * m[p] + (1.f - b1) * g;
     float vv = b2 * v[p] + (1.f - b2) * g * g;
     m[p] = mm;
@@ -274,8 +281,8 @@ int launch_mlp_train_step(float* master, float* work, float* m, float* v, const 
     const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
     const int nblk = mlp_partial_rows(n);
     hipLaunchKernelGGL(mlp_grad_kernel, dim3(nblk), dim3(64), 0, st, work, feat, tgt, perm, base, n, partial, loss_part);
-    hipLaunchKernelGGL(mlp_reduce_adam_kernel, dim3((kNParam + 255) / 256), dim3(256), 0, st, partial, loss_part, nblk,
-                       1.0f / (float)n, loss, master, work, m, v, lr, b1, b2, eps, c1, c2);
+    hipLaunchKernelGGL(mlp_reduce_adam_kernel, dim3((kNParam + kRedParams - 1) / kRedParams), dim3(kRedThreads), 0, st,
+                       partial, loss_part, nblk, 1.0f / (float)n, loss, master, work, m, v, lr, b1, b2, eps, c1, c2);
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
