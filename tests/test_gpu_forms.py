@@ -90,6 +90,30 @@ def test_sparse_wide_blocks_fp64_exact(cols):
     print(f"tfim L=10 wide blocks, {cols} trajectories per block:", _exact(ctx, r, n))
 
 
+def test_sparse_small_blocks_fp64_exact():
+    """d <= 512 with enough trajectories to occupy small blocks: 64 threads of four rows
+    each at d = 256 (Ising chain L = 8), 4,096 trajectories in the batched form; sampled
+    trajectories recomputed one by one by the oracle."""
+    s = w.tfim(L=8, t_end=4.0, n_t=41)
+    n = 4096
+    ctx = _gpu(s, n, seed=9, form=qtm.FORM_BATCHED)
+    st = ctx.stats()
+    assert st["threads"] == 64, st
+    X = ctx.traj_expect()
+    jt, jc, jn = _jumps(ctx, n)
+    worst = 0.0
+    for i in range(0, n, n // 16):
+        r = oracle.run(s, 1, seed=9, traj_begin=i, jcap=32)
+        assert jn[i] == r["jump_counts"][0], i
+        m = min(int(jn[i]), 32)
+        assert np.array_equal(jc[i, :m], r["jump_channels"][0, :m])
+        if m:
+            worst = max(worst, float(np.max(np.abs(jt[i, :m] - r["jump_times"][0, :m]))))
+        assert np.max(np.abs(X[i] - r["X"][0])) <= 1e-8
+    assert worst <= JT_TOL, worst
+    print(f"tfim L=8, 64-thread blocks: worst jump-time difference {worst:.2e}")
+
+
 def test_sparse_fp32_products_statistical():
     s = w.tfim(L=6, t_end=5.0, n_t=26)
     n = 3000
