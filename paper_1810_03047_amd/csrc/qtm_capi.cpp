@@ -962,8 +962,22 @@ int qtm_run(qtm_ctx* ctx, int64_t ntraj, uint64_t seed) { return qtm_run_range(c
 static int enqueue_run(qtm_ctx* c, const qtm::RunArgs& a, long long count, hipStream_t st, qtm::LaunchInfo* li,
                        double* const* avg = nullptr) {
     const int segc = a.seg_cap;
+    // the clearing of outputs and counters, up to qtm::kFillSet buffers per fill launch
+    qtm::FillSet fs{};
+    auto flush = [&]() {
+        const int r = fs.count ? qtm::launch_fills(fs, st) : 0;
+        fs.count = 0;
+        return r ? fail(QTM_E_DEVICE, "fill kernel launch failed") : QTM_OK;
+    };
     auto fill = [&](void* p, size_t bytes, unsigned long long v) {
-        return qtm::launch_fill(p, bytes, v, st) ? fail(QTM_E_DEVICE, "fill kernel launch failed") : QTM_OK;
+        if (bytes % 8 != 0) return fail(QTM_E_DEVICE, "fill of %zu bytes", bytes);
+        if (bytes == 0) return QTM_OK;
+        if (fs.count == qtm::kFillSet) { const int r = flush(); if (r) return r; }
+        fs.p[fs.count] = (unsigned long long*)p;
+        fs.n[fs.count] = (long long)(bytes / 8);
+        fs.v[fs.count] = v;
+        ++fs.count;
+        return QTM_OK;
     };
     int rc;
     for (auto& S : c->sys) {
@@ -977,6 +991,7 @@ static int enqueue_run(qtm_ctx* c, const qtm::RunArgs& a, long long count, hipSt
     if ((rc = fill(c->d_counters, 4 * sizeof(unsigned long long), 0))) return rc;
     if ((rc = fill(c->d_cursor, 4 * sizeof(unsigned long long), 0))) return rc;
     if (c->d_cls_cur && (rc = fill(c->d_cls_cur, 24 * sizeof(unsigned int), 0))) return rc;
+    if ((rc = flush())) return rc;
 
     if (qtm::launch_stamp(c->d_stamp, st)) return fail(QTM_E_DEVICE, "timestamp kernel launch failed");
     const bool one_launch = c->batch && c->sys.size() > 1 && (c->o.form & QTM_FORM_BATCHED);

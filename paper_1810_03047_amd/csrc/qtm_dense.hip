@@ -58,6 +58,9 @@ __global__ void average_partial_kernel(const double2* X, long long count, int m,
     const long long q0 = (long long)c * per;
     const long long q1 = q0 + per < count ? q0 + per : count;
     double sr = 0.0, si = 0.0, s2 = 0.0;
+    // unrolled: the loads of eight trajectories are issued ahead of their additions, which
+    // keep trajectory order
+#pragma unroll 8
     for (long long q = q0; q < q1; ++q) {
         const double2 x = X[q * m + i];
         sr += x.x; si += x.y; s2 += x.x * x.x;
@@ -71,6 +74,7 @@ __global__ void average_final_kernel(const double* part, int nchunk, int m, doub
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= m) return;
     double sr = 0.0, si = 0.0, s2 = 0.0;
+#pragma unroll 8
     for (int c = 0; c < nchunk; ++c) {
         sr += part[((size_t)0 * nchunk + c) * m + i];
         si += part[((size_t)1 * nchunk + c) * m + i];
@@ -166,6 +170,16 @@ __global__ void fill_words_kernel(unsigned long long* p, long long n, unsigned l
         p[i] = v;
 }
 
+// The fills of a FillSet in one launch: the grid strides over each buffer in turn.
+__global__ void fill_set_kernel(FillSet f) {
+    const long long stride = (long long)gridDim.x * blockDim.x, t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int j = 0; j < f.count; ++j) {
+        unsigned long long* p = f.p[j];
+        const unsigned long long v = f.v[j];
+        for (long long i = t; i < f.n[j]; i += stride) p[i] = v;
+    }
+}
+
 // Device timestamp (constant-rate wall clock) for timing a stretch of a stream; a
 // kernel, unlike an event, can be captured into a graph.
 __global__ void stamp_kernel(unsigned long long* t) { t[0] = wall_clock64(); }
@@ -182,6 +196,16 @@ int launch_fill(void* p, size_t bytes, unsigned long long v, hipStream_t st) {
     long long blocks = (n + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(fill_words_kernel, dim3((unsigned)blocks), dim3(256), 0, st, (unsigned long long*)p, n, v);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int launch_fills(const FillSet& f, hipStream_t st) {
+    long long nmax = 0;
+    for (int j = 0; j < f.count; ++j) nmax = f.n[j] > nmax ? f.n[j] : nmax;
+    if (f.count < 1 || f.count > kFillSet || nmax == 0) return f.count == 0 || nmax == 0 ? 0 : -1;
+    long long blocks = (nmax + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(fill_set_kernel, dim3((unsigned)blocks), dim3(256), 0, st, f);
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 

@@ -114,6 +114,15 @@ size_t average_part_size(int m, long long count);
 int launch_average(const DevSystem& s, double* part, double* sum, double* sumsq, hipStream_t st);
 // fills bytes (a multiple of 8) with the 8-byte pattern v (graph-capturable clearing)
 int launch_fill(void* p, size_t bytes, unsigned long long v, hipStream_t st);
+// several fills in one launch (buffer i: n[i] 8-byte words set to v[i])
+constexpr int kFillSet = 8;
+struct FillSet {
+    unsigned long long* p[kFillSet];
+    long long n[kFillSet];
+    unsigned long long v[kFillSet];
+    int count;
+};
+int launch_fills(const FillSet& f, hipStream_t st);
 // writes the device wall clock (hipDeviceAttributeWallClockRate kHz) to *t
 int launch_stamp(unsigned long long* t, hipStream_t st);
 int dense_occupancy(int max_d, int prec, int tile_cols, int* blocks_per_cu, int* lds);
