@@ -51,3 +51,15 @@ def test_mlp_constants_match_architecture():
     hdr = open(os.path.join(ROOT, "include", "qtm.h")).read()
     assert f"#define QTM_MLP_NPARAM {qtm.MLP_NPARAM}" in hdr
     assert f"#define QTM_MLP_NTOTAL {qtm.MLP_NTOTAL}" in hdr
+
+
+@pytest.mark.skipif(not os.path.exists(qtm.LIB_PATH), reason="libqtm.so not built")
+def test_invalid_options_rejected_before_any_device_call():
+    """Option checks come first in qtm_create, so they run without a GPU."""
+    import workloads as w
+    s = w.two_level()
+    for bad in (dict(chunk_traj=-1), dict(team_waves=-1), dict(tile_cols=-2), dict(class_waves=(5, 0, 0)),
+                dict(rtol=0.0), dict(precision=7), dict(integrator=9)):
+        with pytest.raises(qtm.QtmError) as e:
+            qtm.create_system(s, qtm.Opts(**bad))
+        assert e.value.code == qtm.E_INVAL, bad
