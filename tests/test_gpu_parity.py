@@ -111,16 +111,18 @@ def test_batched_persistent_equals_plain():
     assert np.array_equal(a["X"], b["X"])
 
 
-def test_chunked_run_equals_single_run():
+@pytest.mark.parametrize("form", [0, qtm.FORM_BATCHED])
+def test_chunked_run_equals_single_run(form):
     """A run that keeps no per-trajectory data goes chunk by chunk when it holds more
     trajectories than a chunk: the same trajectories (same statistics) and the same
-    sums up to the order of the FP64 additions."""
+    sums up to the order of the FP64 additions.  In the batched form the full chunks
+    replay one captured graph and the last, smaller one takes another."""
     s = w.jaynes_cummings(N=6, t_end=4.0, n_t=41)
     n = 100
-    print(f"[gpu] chunked run jcm N=6 n={n}", flush=True)
+    print(f"[gpu] chunked run jcm N=6 n={n} form={form}", flush=True)
     res = {}
     for chunk in (0, 7, 33):
-        ctx = qtm.create_system(s, qtm.Opts(chunk_traj=chunk))
+        ctx = qtm.create_system(s, qtm.Opts(chunk_traj=chunk, form=form))
         ctx.run(n, 5)
         st = ctx.stats()
         sums = ctx.sums()
@@ -138,7 +140,7 @@ def test_chunked_run_equals_single_run():
         assert np.allclose(q1, q0, rtol=1e-13, atol=1e-13), chunk
         assert np.allclose(m1, m0, rtol=1e-13, atol=1e-13), chunk
     # a context that keeps per-trajectory data never chunks
-    ctx = qtm.create_system(s, qtm.Opts(chunk_traj=7, keep_traj=1))
+    ctx = qtm.create_system(s, qtm.Opts(chunk_traj=7, keep_traj=1, form=form))
     ctx.run(n, 5)
     assert ctx.traj_expect().shape[0] == n
     ctx.destroy()
