@@ -330,6 +330,27 @@ def test_learned_form_matches_oracle_with_same_weights():
     print("attempted steps learned", r["stats"][:, :2].sum(), "plain", plain["stats"][:, :2].sum())
 
 
+def test_learned_form_fp64_exact_on_the_headline_instance():
+    """The learned + batched form at d = 40 (Jaynes-Cummings N = 20) on the banded single-
+    wave team (the headline's instance, here with FP64 products): with the same BF16
+    weights the oracle takes the same steps, jumps and outputs, trajectory by trajectory."""
+    rng = np.random.default_rng(5)
+    s = w.jaynes_cummings(N=20, t_end=6.0, n_t=61)
+    f_ops = _jcm_feature_ops(20)
+    p = _random_proposal(rng, log_h=np.log(0.06))
+    n = 64
+    print(f"[gpu] learned form jcm N=20 ntraj={n} team_waves=1", flush=True)
+    ctx = qtm.create_system(s, qtm.Opts(form=qtm.FORM_LEARNED | qtm.FORM_BATCHED, team_waves=1, record_jumps=32,
+                                        keep_traj=1))
+    ctx.set_proposal(p, f_ops)
+    ctx.run(n, 11)
+    assert ctx.stats()["team_shape"] == 1501, ctx.stats()["team_shape"]      # banded, 5 row tiles, 1 wave
+    r = oracle.run(s, n, seed=11, jcap=32, mlp=_working_params(p), f_ops=f_ops)
+    print("learned jcm N=20:", _exact(ctx, r, n))
+    st = ctx.stats()
+    assert st["accepted"] == int(r["stats"][:, 0].sum()) and st["rejected"] == int(r["stats"][:, 1].sum())
+
+
 def test_segment_records_for_training():
     s = w.jaynes_cummings(N=10, t_end=8.0, n_t=81)
     f_ops = _jcm_feature_ops(10)
