@@ -11,9 +11,10 @@
 // column), as in the kernels' inference; the weight gradients, contractions over
 // samples, are products of activation tiles staged in LDS with the sample index as
 // the contraction index.  A block takes 16-sample tiles blk, blk + nblk, ... and
-// writes its summed gradients to a partial row.  mlp_reduce_kernel sums the partial
-// rows in block order (the result does not depend on scheduling) and scales by
-// 1/batch.
+// writes its summed gradients to a partial row.  mlp_reduce_kernel (a gradient alone)
+// and mlp_reduce_adam_kernel (a training step: the gradient, then Adam) sum the
+// partial rows in a fixed order (the result does not depend on scheduling) and scale
+// by 1/batch.
 #include <hip/hip_runtime.h>
 #include "qtm_internal.h"
 #include <algorithm>
